@@ -1,0 +1,168 @@
+/*
+ * sc.h - all-edge spanning centrality (AESC) on AMD MI355X (gfx950).
+ *
+ * Spanning centrality s(e) of an edge e of a connected undirected graph is the
+ * fraction of spanning trees that contain e (Definition 2.1); it equals the
+ * effective resistance between the endpoints (Section 2.3).  This library
+ * returns an estimate s^(e) for every edge with |s^(e) - s(e)| <= eps
+ * (Definition 2.2, Eq. 1) using the truncated series of Eq. 2:
+ *
+ *   s_tau(e_ij) = sum_{l=0..tau} p_l(i,i)/d_i + p_l(j,j)/d_j - 2 p_l(j,i)/d_i
+ *
+ * with p_l(x,i) = (D^-1 A)^l [x,i] (Table 1), computed either by
+ * deterministic traversal of every source column (TGT, Algorithm 2) or by a
+ * traversal head plus a random-walk tail (TGT+, Algorithm 4).
+ *
+ * Conventions for every entry point:
+ *   - return value: SC_OK (0) or a negative SC_E* code; no C++ exception
+ *     crosses this boundary;
+ *   - on error no output buffer is written and partial allocations are freed;
+ *     sc_last_error() returns a text description of the calling thread's
+ *     last error;
+ *   - a graph handle is not thread-safe; distinct handles are independent;
+ *   - pointers named *_host are host memory; "out" and the optional trace
+ *     arrays are host memory unless SC_DEVICE_PTRS is set in the options'
+ *     flags, in which case they are device memory on the handle's device
+ *     and results are stream-ordered on the options' stream;
+ *   - with host outputs every call returns after the results are written.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+enum {
+  SC_OK = 0,
+  SC_EINVAL = -1,        /* bad argument (size, range, eps not in (0,1), L < 0, ...) */
+  SC_ESELFLOOP = -2,     /* an edge (i,i): A must be 0/1 off the diagonal (Section 2.1) */
+  SC_EDUP = -3,          /* the same undirected edge twice (without SC_MERGE_DUPS) */
+  SC_EDISCONNECTED = -4, /* SC is defined for connected graphs (Definition 2.1) */
+  SC_EBIPARTITE = -5,    /* the series needs a non-bipartite graph (Section 2.1) */
+  SC_ENOMEM = -6,        /* device or host allocation failed */
+  SC_EHIP = -7,          /* a HIP runtime call failed (text in sc_last_error) */
+  SC_ENOTIMPL = -8       /* option combination not supported */
+};
+
+/* build flags (sc_build_graph) */
+#define SC_MERGE_DUPS 0x2u   /* merge repeated edges instead of failing with SC_EDUP */
+
+/* run flags (sc_options.flags) */
+#define SC_DEVICE_PTRS 0x1u  /* out / trace arrays are device pointers */
+#define SC_TIME_KERNELS 0x4u /* bracket every propagation launch with HIP events (stats) */
+
+/* methods (sc_options.method) */
+#define SC_TGT 0       /* Algorithm 2: traversal to tau for every source */
+#define SC_TGT_PLUS 1  /* Algorithm 4: traversal to tilde_tau, then random walks */
+
+typedef struct sc_graph sc_graph;   /* opaque: device CSR, maps, work buffers */
+
+typedef struct sc_options {
+  int method;          /* SC_TGT or SC_TGT_PLUS                                      */
+  int precision;       /* 0: FP32 propagation, 1: FP64 propagation; sums always FP64 */
+  int block;           /* source-block width B (columns per pass): 0 = default      */
+  int gamma;           /* candidate count of Algorithm 3; < 0 means 10 (Section 5.1) */
+  double delta;        /* TGT+ failure probability; <= 0 means 1/n (Section 5.1)     */
+  uint64_t seed;       /* Philox4x32-10 key for the walks                            */
+  int tilde_tau;       /* TGT+ switch step: < 0 = chosen by the cost model          */
+  int max_L;           /* cap on automatic truncation lengths (<= 0: 255)            */
+  double lambda_star;  /* > 0: use this value of max_{k>=2}|lambda_k|; else computed  */
+  unsigned flags;      /* SC_DEVICE_PTRS | SC_TIME_KERNELS                           */
+  void* stream;        /* hipStream_t to run on; NULL = the null stream             */
+  /* optional trace outputs (NULL = not wanted); same memory kind as out */
+  int32_t* tau_out;        /* [m]  truncation tau_ij used per input edge             */
+  int32_t* tilde_tau_out;  /* [n]  switch step per source node (TGT: tau_p)          */
+  int64_t* nr_out;         /* [2m] walk pairs per half-edge: [0,m) = (u_e -> v_e),
+                                   [m,2m) = (v_e -> u_e)                            */
+} sc_options;
+
+typedef struct sc_stats {
+  int L_used;              /* largest truncation used                                  */
+  int L_min;               /* smallest truncation used                                 */
+  int tilde_tau;           /* TGT+ switch step used (uniform over sources), else -1   */
+  int block;               /* source-block width used                                  */
+  double lambda_star;      /* value used for automatic truncation (0 if not needed)   */
+  int64_t walks;           /* walk pairs simulated                                    */
+  int64_t walk_steps;      /* single-walk steps simulated                             */
+  int64_t prop_launches;   /* dense propagation launches                              */
+  double prop_ms;          /* sum of propagation launch times (SC_TIME_KERNELS)       */
+  double prop_bytes;       /* algorithmic bytes of all propagation launches           */
+  double total_ms;         /* wall time of the call on the stream                     */
+} sc_stats;
+
+/* Fill *o with defaults: TGT, FP32, gamma 10, delta 1/n, seed 0x5C5C, auto tilde_tau. */
+void sc_default_options(sc_options* o);
+
+/*
+ * Build a graph handle from an undirected edge list (Section 2.1: simple,
+ * unweighted).  u_host/v_host: m node ids each in [0, n), int64, host
+ * memory, copied (the caller keeps ownership).  Edge e = (u_host[e],
+ * v_host[e]); results are reported per e in this order.  Checks: ids in
+ * range (SC_EINVAL), no self-loops (SC_ESELFLOOP), no repeated edge
+ * (SC_EDUP unless SC_MERGE_DUPS), connected (SC_EDISCONNECTED), not
+ * bipartite (SC_EBIPARTITE).  With SC_MERGE_DUPS repeated edges report the
+ * same value.  The CSR, degree and half-edge maps are uploaded to the
+ * current HIP device.  n >= 2, 1 <= m, 2m < 2^31.
+ */
+int sc_build_graph(int64_t n, int64_t m, const int64_t* u_host, const int64_t* v_host,
+                   unsigned flags, sc_graph** out);
+
+/* Node and edge counts of a handle. */
+int sc_graph_size(const sc_graph* g, int64_t* n, int64_t* m);
+
+/* Release a handle and all device memory it owns.  NULL is allowed. */
+void sc_free_graph(sc_graph* g);
+
+/*
+ * lambda* = max_{k>=2} |lambda_k| of D^-1/2 A D^-1/2 (Lemma 3.1), the rate in
+ * the truncation bound of Theorem 3.2 (Algorithm 1 line 1).  Computed once by
+ * Lanczos on the GPU (deflated of the top eigenvector sqrt(d)/sqrt(2m)) and
+ * cached in the handle.  The value returned is an upper estimate: the
+ * extreme Ritz value plus its residual norm.
+ */
+int sc_lambda_star(sc_graph* g, double* lam);
+
+/*
+ * All-edge SC with default options (FP32 propagation, TGT when L > 0 or
+ * TGT+ with automatic truncation when L == 0).
+ *   eps : absolute error target, in (0, 1) (Definition 2.2).
+ *   L   : > 0  every edge uses tau = L rounded up to odd (Eq. 5 parity);
+ *         == 0 per-edge tau_ij from Theorem 3.2 with lambda* (Eq. 6 with
+ *              Upsilon = Delta = 0), at eps for TGT and eps/2 for TGT+
+ *              (Algorithm 4 line 2);
+ *         < 0 SC_EINVAL.
+ *   out : m doubles, host memory, input edge order.
+ */
+int sc_all_edges(sc_graph* g, double eps, int L, double* out);
+
+/*
+ * All-edge SC with explicit options; st (may be NULL) receives statistics.
+ * TGT (Algorithm 2): for every source i and l = 1..tau_ij every half-edge
+ * (i,j) gains (p_l(i,i) - p_l(j,i))/d_i (Eq. 9); s = g(i,j) + g(j,i).
+ * TGT+ (Algorithm 4): the traversal stops at tilde_tau; each half-edge with
+ * tau_ij > tilde_tau adds the mean of n_r samples of X (Eq. 11), n_r from
+ * Eq. 13 with chi from Algorithm 3 / Eq. 17 (Eq. 15 when gamma == 0).
+ * Random walks follow the Philox4x32-10 counter scheme documented in the
+ * implementation (counter = (i, j, r, side*2^31 + step/4), key = seed).
+ */
+int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double* out,
+                    sc_stats* st);
+
+/* Text for an error code; never NULL. */
+const char* sc_strerror(int code);
+
+/* Text of the calling thread's last error; never NULL. */
+const char* sc_last_error(void);
+
+/* Library version string. */
+const char* sc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SC_H */

@@ -297,21 +297,23 @@ def tail_exact(g, q, i, j, length):
     return tot / g.degf[i]
 
 
-def tgt_plus_replay(g, tau_edge, tilde_tau, nr_uv, nr_vu, seed):
+def tgt_plus_replay(g, tau_edge, tilde_tau, nr_uv, nr_vu, seed, sources=None):
     """Algorithm 4 with tilde_tau (per source) and n_r (per half-edge) given.
 
     For each source i: traverse to tilde_tau_i collecting g_{tilde_tau} (Alg. 2
     with every half truncated at min(tilde_tau_i, tau_ij)), keep
     q = p_{tilde_tau_i}(., i); for every half (i, j) with
     L' = tau_ij - tilde_tau_i > 0 add the mean of n_r samples of X (Eq. 11).
-    Returns g_uv, g_vu and s = g_uv + g_vu (Algorithm 4 line 18)."""
+    Returns g_uv, g_vu and s = g_uv + g_vu (Algorithm 4 line 18).  With
+    ``sources`` only those sources' halves are computed (others are NaN)."""
     g = as_graph(g)
     tau_edge = np.asarray(tau_edge, dtype=np.int64)
     tilde_tau = np.asarray(tilde_tau, dtype=np.int64)
     nr = np.concatenate([np.asarray(nr_uv, np.int64), np.asarray(nr_vu, np.int64)])
     tau_half = np.concatenate([tau_edge, tau_edge])
-    gh = np.empty(2 * g.m)
-    for i in range(g.n):
+    gh = np.full(2 * g.m, np.nan)
+    src = range(g.n) if sources is None else [int(x) for x in sources]
+    for i in src:
         H = g.halves_of([i])
         if len(H) == 0:
             continue

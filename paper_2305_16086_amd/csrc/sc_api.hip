@@ -1,0 +1,900 @@
+// Host side of libsc: graph ingest and validation, the truncation policy,
+// the TGT / TGT+ orchestration over source blocks, and lambda* by Lanczos.
+//
+// Every piece of arithmetic of the method runs in the kernels of
+// kernels_tgt.hip / kernels_plus.hip; this file only builds the CSR, sizes
+// buffers, chooses launch parameters and sequences the launches.
+#include "sc_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      return fail(e_ == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,                 \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    }                                                                              \
+  } while (0)
+
+template <typename P>
+hipError_t dev_alloc(P** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(P));
+}
+
+template <typename P>
+void dev_free(P*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct sc_graph {
+  sc::DeviceGraph d;
+  int device = 0;
+  std::vector<int32_t> rowptr_h;
+  std::vector<int32_t> deg_h;
+  double lambda_star = -1.0;
+
+  // work buffers, grown on demand
+  void* Y[2] = {nullptr, nullptr};
+  size_t ybytes = 0;
+  void* partials = nullptr;
+  size_t pbytes = 0;
+  unsigned long long* mask = nullptr;
+  double* gacc = nullptr;
+  int32_t* tau_slot = nullptr;
+  int32_t* tau_row = nullptr;
+  int64_t* nr_slot = nullptr;
+  sc::ColStats* cs = nullptr;
+  unsigned long long* work = nullptr;
+  double* out_dev = nullptr;
+  int32_t* tau_out_dev = nullptr;
+  int32_t* tilde_out_dev = nullptr;
+  int64_t* nr_out_dev = nullptr;
+  std::vector<hipEvent_t> events;
+
+  void release() {
+    dev_free(d.rowptr);
+    dev_free(d.col);
+    dev_free(d.deg);
+    dev_free(d.slot_row);
+    dev_free(d.slot_half);
+    dev_free(d.half_slot);
+    dev_free(d.inv_deg_f);
+    dev_free(d.inv_deg_d);
+    dev_free(d.tasks);
+    dev_free(d.heavy);
+    if (Y[0]) (void)hipFree(Y[0]);
+    if (Y[1]) (void)hipFree(Y[1]);
+    Y[0] = Y[1] = nullptr;
+    if (partials) (void)hipFree(partials);
+    partials = nullptr;
+    dev_free(mask);
+    dev_free(gacc);
+    dev_free(tau_slot);
+    dev_free(tau_row);
+    dev_free(nr_slot);
+    dev_free(cs);
+    dev_free(work);
+    dev_free(out_dev);
+    dev_free(tau_out_dev);
+    dev_free(tilde_out_dev);
+    dev_free(nr_out_dev);
+    for (auto& e : events) (void)hipEventDestroy(e);
+    events.clear();
+  }
+};
+
+// ====================================================================== graph build
+
+extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                              unsigned flags, sc_graph** out) {
+  if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  if (!u || !v) return fail(SC_EINVAL, "edge arrays are NULL");
+  if (n < 2 || m < 1) return fail(SC_EINVAL, "need n >= 2 and m >= 1");
+  if (n >= (1ll << 31) || 2 * m >= (1ll << 31))
+    return fail(SC_EINVAL, "n and 2m must be below 2^31");
+  for (int64_t e = 0; e < m; ++e) {
+    if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n)
+      return fail(SC_EINVAL, "edge " + std::to_string(e) + " has a node id out of [0, n)");
+    if (u[e] == v[e]) return fail(SC_ESELFLOOP, "edge " + std::to_string(e) + " is a self-loop");
+  }
+  const int32_t N = static_cast<int32_t>(n);
+  const int64_t H = 2 * m;
+  std::vector<int32_t> hsrc, hdst;
+  std::vector<int32_t> order, tmp;
+  try {
+    hsrc.resize(H);
+    hdst.resize(H);
+    order.resize(H);
+    tmp.resize(H);
+  } catch (const std::bad_alloc&) {
+    return fail(SC_ENOMEM, "host allocation failed");
+  }
+  for (int64_t e = 0; e < m; ++e) {
+    hsrc[e] = static_cast<int32_t>(u[e]);
+    hdst[e] = static_cast<int32_t>(v[e]);
+    hsrc[e + m] = static_cast<int32_t>(v[e]);
+    hdst[e + m] = static_cast<int32_t>(u[e]);
+  }
+  // two stable counting sorts: by neighbour, then by source -> rows sorted by neighbour
+  std::vector<int64_t> cnt(static_cast<size_t>(N) + 1);
+  auto counting_sort = [&](const std::vector<int32_t>& key, const std::vector<int32_t>& in,
+                           std::vector<int32_t>& outv) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t i = 0; i < H; ++i) ++cnt[key[in[i]] + 1];
+    for (int32_t x = 0; x < N; ++x) cnt[x + 1] += cnt[x];
+    for (int64_t i = 0; i < H; ++i) outv[cnt[key[in[i]]]++] = in[i];
+  };
+  std::iota(order.begin(), order.end(), 0);
+  counting_sort(hdst, order, tmp);
+  counting_sort(hsrc, tmp, order);
+
+  // rows, duplicates
+  std::vector<int32_t> rowptr(N + 1, 0), col, slot_half, half_slot(H);
+  col.reserve(H);
+  slot_half.reserve(H);
+  int64_t i = 0;
+  for (int32_t x = 0; x < N; ++x) {
+    rowptr[x] = static_cast<int32_t>(col.size());
+    while (i < H && hsrc[order[i]] == x) {
+      const int32_t h = order[i];
+      if (!col.empty() && static_cast<int64_t>(col.size()) > rowptr[x] && col.back() == hdst[h]) {
+        if (!(flags & SC_MERGE_DUPS)) {
+          const int64_t e = h % m;
+          return fail(SC_EDUP, "edge " + std::to_string(e) + " repeats an earlier edge");
+        }
+        half_slot[h] = static_cast<int32_t>(col.size()) - 1;
+      } else {
+        half_slot[h] = static_cast<int32_t>(col.size());
+        col.push_back(hdst[h]);
+        slot_half.push_back(h);
+      }
+      ++i;
+    }
+  }
+  rowptr[N] = static_cast<int32_t>(col.size());
+  const int64_t S = static_cast<int64_t>(col.size());
+  std::vector<int32_t> deg(N), slot_row(S);
+  for (int32_t x = 0; x < N; ++x) {
+    deg[x] = rowptr[x + 1] - rowptr[x];
+    for (int32_t k = rowptr[x]; k < rowptr[x + 1]; ++k) slot_row[k] = x;
+  }
+
+  // connected and non-bipartite (BFS 2-colouring)
+  {
+    std::vector<int8_t> colour(N, -1);
+    std::vector<int32_t> queue;
+    queue.reserve(N);
+    queue.push_back(0);
+    colour[0] = 0;
+    bool odd_cycle = false;
+    for (size_t qh = 0; qh < queue.size(); ++qh) {
+      const int32_t x = queue[qh];
+      for (int32_t k = rowptr[x]; k < rowptr[x + 1]; ++k) {
+        const int32_t y = col[k];
+        if (colour[y] < 0) {
+          colour[y] = static_cast<int8_t>(1 - colour[x]);
+          queue.push_back(y);
+        } else if (colour[y] == colour[x]) {
+          odd_cycle = true;
+        }
+      }
+    }
+    if (static_cast<int64_t>(queue.size()) != N)
+      return fail(SC_EDISCONNECTED, "graph is not connected");
+    if (!odd_cycle) return fail(SC_EBIPARTITE, "graph is bipartite");
+  }
+
+  // propagation tasks: chunks of heavy rows first, then whole rows
+  std::vector<sc::Task> tasks;
+  std::vector<sc::HeavyRow> heavy;
+  int32_t nparts = 0;
+  for (int32_t x = 0; x < N; ++x) {
+    if (deg[x] > sc::kChunk) {
+      sc::HeavyRow hr{x, nparts, 0, 0};
+      for (int32_t b = rowptr[x]; b < rowptr[x + 1]; b += sc::kChunk) {
+        tasks.push_back({x, b, std::min(b + sc::kChunk, rowptr[x + 1]), nparts++});
+        ++hr.nparts;
+      }
+      heavy.push_back(hr);
+    }
+  }
+  for (int32_t x = 0; x < N; ++x)
+    if (deg[x] <= sc::kChunk) tasks.push_back({x, rowptr[x], rowptr[x + 1], -1});
+
+  std::vector<float> inv_f(N);
+  std::vector<double> inv_d(N);
+  for (int32_t x = 0; x < N; ++x) {
+    inv_f[x] = 1.0f / static_cast<float>(deg[x]);
+    inv_d[x] = 1.0 / static_cast<double>(deg[x]);
+  }
+
+  sc_graph* g = new (std::nothrow) sc_graph();
+  if (!g) return fail(SC_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&g->device);
+  g->d.n = N;
+  g->d.m = m;
+  g->d.nslots = S;
+  g->d.ntasks = static_cast<int32_t>(tasks.size());
+  g->d.nheavy = static_cast<int32_t>(heavy.size());
+  g->d.nparts = nparts;
+  auto up = [&](auto** dst, const auto& src) -> hipError_t {
+    hipError_t e = dev_alloc(dst, src.size());
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(src[0]), hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(&g->d.rowptr, rowptr);
+  if (e == hipSuccess) e = up(&g->d.col, col);
+  if (e == hipSuccess) e = up(&g->d.deg, deg);
+  if (e == hipSuccess) e = up(&g->d.slot_row, slot_row);
+  if (e == hipSuccess) e = up(&g->d.slot_half, slot_half);
+  if (e == hipSuccess) e = up(&g->d.half_slot, half_slot);
+  if (e == hipSuccess) e = up(&g->d.inv_deg_f, inv_f);
+  if (e == hipSuccess) e = up(&g->d.inv_deg_d, inv_d);
+  if (e == hipSuccess) e = up(&g->d.tasks, tasks);
+  if (e == hipSuccess) e = up(&g->d.heavy, heavy);
+  if (e != hipSuccess) {
+    g->release();
+    delete g;
+    return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
+                std::string("graph upload: ") + hipGetErrorString(e));
+  }
+  g->rowptr_h = std::move(rowptr);
+  g->deg_h = std::move(deg);
+  *out = g;
+  return SC_OK;
+}
+
+extern "C" int sc_graph_size(const sc_graph* g, int64_t* n, int64_t* m) {
+  if (!g) return fail(SC_EINVAL, "graph is NULL");
+  if (n) *n = g->d.n;
+  if (m) *m = g->d.m;
+  return SC_OK;
+}
+
+extern "C" void sc_free_graph(sc_graph* g) {
+  if (!g) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  g->release();
+  (void)hipSetDevice(cur);
+  delete g;
+}
+
+// ====================================================================== lambda* by Lanczos
+
+namespace {
+
+// Cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major k x k).
+// On return a holds the eigenvalues on its diagonal and vec the eigenvectors (columns).
+void jacobi_eigen(std::vector<double>& a, std::vector<double>& vec, int k) {
+  vec.assign(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) vec[static_cast<size_t>(i) * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = 0; q < k; ++q) {
+        const double x = a[static_cast<size_t>(p) * k + q];
+        tot += x * x;
+        if (p != q) off += x * x;
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[static_cast<size_t>(p) * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = a[static_cast<size_t>(p) * k + p];
+        const double aqq = a[static_cast<size_t>(q) * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0);
+        const double s = t * c;
+        for (int r = 0; r < k; ++r) {  // A <- A J (columns p, q)
+          const double arp = a[static_cast<size_t>(r) * k + p];
+          const double arq = a[static_cast<size_t>(r) * k + q];
+          a[static_cast<size_t>(r) * k + p] = c * arp - s * arq;
+          a[static_cast<size_t>(r) * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // A <- J^T A (rows p, q)
+          const double apr = a[static_cast<size_t>(p) * k + r];
+          const double aqr = a[static_cast<size_t>(q) * k + r];
+          a[static_cast<size_t>(p) * k + r] = c * apr - s * aqr;
+          a[static_cast<size_t>(q) * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = vec[static_cast<size_t>(r) * k + p];
+          const double vrq = vec[static_cast<size_t>(r) * k + q];
+          vec[static_cast<size_t>(r) * k + p] = c * vrp - s * vrq;
+          vec[static_cast<size_t>(r) * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+}
+
+__global__ void k_scale_into(const double* __restrict__ w, double s, double* __restrict__ dst,
+                             int64_t n) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < n) dst[x] = w[x] * s;
+}
+
+// extreme Ritz estimate: max over the two ends of |theta| + residual
+double ritz_bound(const std::vector<double>& alpha, const std::vector<double>& beta, int k,
+                  double beta_last, double* worst_res) {
+  std::vector<double> a(static_cast<size_t>(k) * k, 0.0), vec;
+  for (int i = 0; i < k; ++i) {
+    a[static_cast<size_t>(i) * k + i] = alpha[i];
+    if (i + 1 < k) {
+      a[static_cast<size_t>(i) * k + i + 1] = beta[i];
+      a[static_cast<size_t>(i + 1) * k + i] = beta[i];
+    }
+  }
+  jacobi_eigen(a, vec, k);
+  int imax = 0, imin = 0;
+  for (int i = 1; i < k; ++i) {
+    if (a[static_cast<size_t>(i) * k + i] > a[static_cast<size_t>(imax) * k + imax]) imax = i;
+    if (a[static_cast<size_t>(i) * k + i] < a[static_cast<size_t>(imin) * k + imin]) imin = i;
+  }
+  const double rmax = std::fabs(beta_last * vec[static_cast<size_t>(k - 1) * k + imax]);
+  const double rmin = std::fabs(beta_last * vec[static_cast<size_t>(k - 1) * k + imin]);
+  const double tmax = a[static_cast<size_t>(imax) * k + imax];
+  const double tmin = a[static_cast<size_t>(imin) * k + imin];
+  *worst_res = std::max(rmax, rmin);
+  return std::max(std::fabs(tmax) + rmax, std::fabs(tmin) + rmin);
+}
+
+int compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
+  const int64_t n = g->d.n;
+  const int kmax = static_cast<int>(std::min<int64_t>(n - 1, 160));
+  const int64_t ld = n;
+  double *V = nullptr, *w = nullptr, *h = nullptr, *sid = nullptr;
+  auto cleanup = [&]() {
+    dev_free(V);
+    dev_free(w);
+    dev_free(h);
+    dev_free(sid);
+  };
+  hipError_t e = dev_alloc(&V, static_cast<size_t>(kmax + 2) * ld);
+  if (e == hipSuccess) e = dev_alloc(&w, n);
+  if (e == hipSuccess) e = dev_alloc(&h, kmax + 2);
+  if (e == hipSuccess) e = dev_alloc(&sid, n);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP, "lanczos allocation failed");
+  }
+  // column 0: the top eigenvector sqrt(d)/sqrt(2m) (eigenvalue 1), deflated throughout
+  std::vector<double> hv(n), sidh(n);
+  const double two_m = static_cast<double>(g->d.nslots);
+  for (int64_t x = 0; x < n; ++x) {
+    hv[x] = std::sqrt(g->deg_h[x] / two_m);
+    sidh[x] = 1.0 / std::sqrt(static_cast<double>(g->deg_h[x]));
+  }
+  // start vector: fixed pseudo-random, made orthogonal to column 0
+  std::vector<double> v0(n);
+  uint64_t z = 0x9E3779B97F4A7C15ull;
+  double dot = 0.0;
+  for (int64_t x = 0; x < n; ++x) {
+    z += 0x9E3779B97F4A7C15ull;
+    uint64_t r = z;
+    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+    r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+    r ^= r >> 31;
+    v0[x] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    dot += v0[x] * hv[x];
+  }
+  double nrm = 0.0;
+  for (int64_t x = 0; x < n; ++x) {
+    v0[x] -= dot * hv[x];
+    nrm += v0[x] * v0[x];
+  }
+  nrm = std::sqrt(nrm);
+  for (int64_t x = 0; x < n; ++x) v0[x] /= nrm;
+  HIP_TRY(hipMemcpy(V, hv.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(V + ld, v0.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(sid, sidh.data(), n * sizeof(double), hipMemcpyHostToDevice));
+
+  std::vector<double> alpha, beta, hh(kmax + 2);
+  double result = -1.0;
+  const unsigned grid = static_cast<unsigned>((n + 255) / 256);
+  for (int j = 1; j <= kmax; ++j) {
+    const double* vj = V + static_cast<size_t>(j) * ld;
+    HIP_TRY(sc::launch_nmat_spmv(g->d, sid, vj, w, st));
+    double a_j = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {   // full re-orthogonalisation, twice
+      HIP_TRY(sc::launch_multi_dot(V, j + 1, ld, w, n, h, st));
+      HIP_TRY(hipMemcpyAsync(hh.data(), h, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      a_j += hh[j];
+      HIP_TRY(sc::launch_multi_axpy(V, j + 1, ld, h, w, n, st));
+    }
+    HIP_TRY(sc::launch_multi_dot(w, 1, ld, w, n, h, st));
+    HIP_TRY(hipMemcpyAsync(hh.data(), h, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double b_j = std::sqrt(std::max(hh[0], 0.0));
+    alpha.push_back(a_j);
+    const bool exhausted = b_j < 1e-12 || j == kmax;
+    if ((j % 20 == 0) || exhausted) {
+      double res = 0.0;
+      const double bound = ritz_bound(alpha, beta, j, exhausted ? 0.0 : b_j, &res);
+      result = bound;
+      if (exhausted || res < 1e-9) break;
+    }
+    beta.push_back(b_j);
+    k_scale_into<<<grid, 256, 0, st>>>(w, 1.0 / b_j, V + static_cast<size_t>(j + 1) * ld, n);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  cleanup();
+  if (!(result > 0.0) || !(result < 1.0))
+    return fail(SC_EINVAL, "lambda* estimate outside (0, 1): " + std::to_string(result) +
+                               " (graph bipartite or too small?)");
+  *out = result;
+  return SC_OK;
+}
+
+}  // namespace
+
+extern "C" int sc_lambda_star(sc_graph* g, double* lam) {
+  if (!g || !lam) return fail(SC_EINVAL, "NULL argument");
+  if (g->lambda_star > 0) {
+    *lam = g->lambda_star;
+    return SC_OK;
+  }
+  double v = 0.0;
+  const int rc = compute_lambda_star(g, nullptr, &v);
+  if (rc != SC_OK) return rc;
+  g->lambda_star = v;
+  *lam = v;
+  return SC_OK;
+}
+
+// ====================================================================== all-edge SC
+
+extern "C" void sc_default_options(sc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = SC_TGT;
+  o->precision = 0;
+  o->block = 0;
+  o->gamma = 10;
+  o->delta = 0.0;
+  o->seed = 0x5C5Cull;
+  o->tilde_tau = -1;
+  o->max_L = 255;
+  o->lambda_star = 0.0;
+}
+
+namespace {
+
+int ensure_buffers(sc_graph* g, int B, size_t tsize) {
+  const int64_t n = g->d.n;
+  const int64_t S = static_cast<int64_t>(g->rowptr_h[n]);
+  const size_t yb = static_cast<size_t>(n) * B * tsize;
+  if (yb > g->ybytes) {
+    for (int i = 0; i < 2; ++i) {
+      if (g->Y[i]) (void)hipFree(g->Y[i]);
+      g->Y[i] = nullptr;
+    }
+    g->ybytes = 0;
+    HIP_TRY(hipMalloc(&g->Y[0], yb));
+    HIP_TRY(hipMalloc(&g->Y[1], yb));
+    g->ybytes = yb;
+  }
+  const size_t pb = static_cast<size_t>(std::max(g->d.nparts, 1)) * B * tsize;
+  if (pb > g->pbytes) {
+    if (g->partials) (void)hipFree(g->partials);
+    g->partials = nullptr;
+    g->pbytes = 0;
+    HIP_TRY(hipMalloc(&g->partials, pb));
+    g->pbytes = pb;
+  }
+  if (!g->mask) {
+    HIP_TRY(dev_alloc(&g->mask, n));
+    HIP_TRY(hipMemset(g->mask, 0, n * sizeof(unsigned long long)));
+  }
+  if (!g->gacc) HIP_TRY(dev_alloc(&g->gacc, S));
+  if (!g->tau_slot) HIP_TRY(dev_alloc(&g->tau_slot, S));
+  if (!g->tau_row) HIP_TRY(dev_alloc(&g->tau_row, n));
+  if (!g->nr_slot) HIP_TRY(dev_alloc(&g->nr_slot, S));
+  if (!g->cs) HIP_TRY(dev_alloc(&g->cs, 64));
+  if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
+  if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
+  return SC_OK;
+}
+
+struct CostModel {
+  double gather_bw;   // bytes/s for the neighbour gathers of one dense step
+  double step_fixed;  // s of fixed overhead per dense step
+  double walk_step;   // s per single-walk step (whole-GPU throughput)
+};
+
+CostModel cost_model() {
+  CostModel c{4.0e12, 6.0e-6, 1.0e-10};
+  if (const char* s = std::getenv("SC_COST_GATHER_BW")) c.gather_bw = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_STEP_FIXED")) c.step_fixed = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_WALK_STEP")) c.walk_step = std::atof(s);
+  return c;
+}
+
+template <typename T>
+struct Runner {
+  sc_graph* g;
+  int B;
+  hipStream_t st;
+  bool timing;
+  sc_stats stats{};
+  size_t ev_used = 0;
+  int cur = 0;   // index of Y holding the current step
+
+  T* Yb(int i) { return static_cast<T*>(g->Y[i]); }
+  T* parts() { return static_cast<T*>(g->partials); }
+
+  int event_pair(hipEvent_t* a, hipEvent_t* b) {
+    while (g->events.size() < ev_used + 2) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      g->events.push_back(e);
+    }
+    *a = g->events[ev_used];
+    *b = g->events[ev_used + 1];
+    ev_used += 2;
+    return SC_OK;
+  }
+
+  double step_bytes() const {
+    const double n = g->d.n, S = static_cast<double>(g->rowptr_h[g->d.n]);
+    return 2.0 * n * B * sizeof(T) + 4.0 * S + 16.0 * g->d.ntasks + sizeof(T) * n;
+  }
+
+  // traverse block [s0, s0+B) from l = 2 up to l = lend, accumulating when acc
+  int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc) {
+    if (lend < 2) return SC_OK;
+    HIP_TRY(sc::launch_mask_set(g->d, s0, B, g->mask, false, st));
+    cur = 0;
+    HIP_TRY(sc::launch_twohop<T>(g->d, B, g->mask, Yb(cur), parts(), st));
+    HIP_TRY(sc::launch_fixup<T>(g->d, B, parts(), Yb(cur), st));
+    HIP_TRY(sc::launch_mask_set(g->d, s0, B, g->mask, true, st));
+    if (acc) HIP_TRY(sc::launch_accumulate<T>(g->d, kbeg, kend, s0, B, 2, Yb(cur), g->tau_slot, gacc, st));
+    for (int ell = 3; ell <= lend; ++ell) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (timing) {
+        int rc = event_pair(&a, &b);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(a, st));
+      }
+      HIP_TRY(sc::launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), st));
+      if (timing) HIP_TRY(hipEventRecord(b, st));
+      ++stats.prop_launches;
+      stats.prop_bytes += step_bytes();
+      HIP_TRY(sc::launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
+      cur = 1 - cur;
+      if (acc) HIP_TRY(sc::launch_accumulate<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), g->tau_slot, gacc, st));
+    }
+    return SC_OK;
+  }
+
+  // Y for l in {0, 1} when the walk tail starts that early
+  int init_low(int s0, int ell) {
+    HIP_TRY(hipMemsetAsync(Yb(0), 0, g->ybytes, st));
+    cur = 0;
+    // p_0 = e_s; p_1(x, s) = 1/d_x for x in N(s): one-hop scatter via the mask kernel's pattern
+    return ell <= 1 ? init_indicator(s0, ell) : SC_OK;
+  }
+  int init_indicator(int s0, int ell);
+};
+
+__global__ void k_init_low_float(int n, int s0, int B, int ell, const int32_t* rowptr,
+                                 const int32_t* col, const float* inv_deg, float* Y) {
+  const int c = blockIdx.x;
+  const int s = s0 + c;
+  if (s >= n) return;
+  if (ell == 0) {
+    if (threadIdx.x == 0) Y[static_cast<size_t>(s) * B + c] = 1.0f;
+    return;
+  }
+  for (int k = rowptr[s] + threadIdx.x; k < rowptr[s + 1]; k += blockDim.x) {
+    const int x = col[k];
+    Y[static_cast<size_t>(x) * B + c] = inv_deg[x];
+  }
+}
+__global__ void k_init_low_double(int n, int s0, int B, int ell, const int32_t* rowptr,
+                                  const int32_t* col, const double* inv_deg, double* Y) {
+  const int c = blockIdx.x;
+  const int s = s0 + c;
+  if (s >= n) return;
+  if (ell == 0) {
+    if (threadIdx.x == 0) Y[static_cast<size_t>(s) * B + c] = 1.0;
+    return;
+  }
+  for (int k = rowptr[s] + threadIdx.x; k < rowptr[s + 1]; k += blockDim.x) {
+    const int x = col[k];
+    Y[static_cast<size_t>(x) * B + c] = inv_deg[x];
+  }
+}
+
+template <>
+int Runner<float>::init_indicator(int s0, int ell) {
+  k_init_low_float<<<B, 64, 0, st>>>(g->d.n, s0, B, ell, g->d.rowptr, g->d.col, g->d.inv_deg_f,
+                                     Yb(0));
+  HIP_TRY(hipGetLastError());
+  return SC_OK;
+}
+template <>
+int Runner<double>::init_indicator(int s0, int ell) {
+  k_init_low_double<<<B, 64, 0, st>>>(g->d.n, s0, B, ell, g->d.rowptr, g->d.col, g->d.inv_deg_d,
+                                      Yb(0));
+  HIP_TRY(hipGetLastError());
+  return SC_OK;
+}
+
+template <typename T>
+int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_user,
+               sc_stats* st_user) {
+  const int64_t n = g->d.n, m = g->d.m;
+  hipStream_t st = static_cast<hipStream_t>(o.stream);
+  const int B = o.block > 0 ? o.block : 64;
+  if (B != 16 && B != 32 && B != 64) return fail(SC_EINVAL, "block must be 16, 32 or 64");
+  const bool plus = o.method == SC_TGT_PLUS;
+  const int gamma = o.gamma < 0 ? 10 : o.gamma;
+  if (gamma > sc::kMaxGamma) return fail(SC_EINVAL, "gamma above 16 is not supported");
+  int max_L = o.max_L > 0 ? o.max_L : 255;
+  if (max_L % 2 == 0) --max_L;
+  int rc = ensure_buffers(g, B, sizeof(T));
+  if (rc) return rc;
+  const bool dev_ptrs = (o.flags & SC_DEVICE_PTRS) != 0;
+
+  Runner<T> R{g, B, st, (o.flags & SC_TIME_KERNELS) != 0};
+  R.stats.block = B;
+  R.stats.tilde_tau = -1;
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  HIP_TRY(hipEventRecord(t0, st));
+
+  // truncation policy
+  double lam = 0.0;
+  int Lodd = 0;
+  if (L > 0) {
+    Lodd = (L % 2 == 1) ? L : L + 1;
+  } else {
+    if (o.lambda_star > 0.0) {
+      lam = o.lambda_star;
+    } else {
+      if (g->lambda_star <= 0.0) {
+        double v = 0.0;
+        rc = compute_lambda_star(g, st, &v);
+        if (rc) return rc;
+        g->lambda_star = v;
+      }
+      lam = g->lambda_star;
+    }
+    if (!(lam > 0.0 && lam < 1.0)) return fail(SC_EINVAL, "lambda* must lie in (0, 1)");
+  }
+  R.stats.lambda_star = lam;
+  const double eps_tau = plus ? eps / 2.0 : eps;
+  HIP_TRY(sc::launch_tau(g->d, Lodd, eps_tau, lam, max_L, g->tau_slot, g->tau_row, st));
+  std::vector<int32_t> tau_row(n);
+  HIP_TRY(hipMemcpyAsync(tau_row.data(), g->tau_row, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int Lmax = 0, Lmin = 1 << 30;
+  for (int64_t x = 0; x < n; ++x) {
+    Lmax = std::max(Lmax, tau_row[x]);
+    Lmin = std::min(Lmin, tau_row[x]);
+  }
+  R.stats.L_used = Lmax;
+  R.stats.L_min = Lmin;
+
+  const int nblocks = static_cast<int>((n + B - 1) / B);
+  auto block_range = [&](int b, int* s0, int* kbeg, int* kend, int* tmax) {
+    *s0 = b * B;
+    const int s1 = static_cast<int>(std::min<int64_t>(n, *s0 + B));
+    *kbeg = g->rowptr_h[*s0];
+    *kend = g->rowptr_h[s1];
+    int t = 0;
+    for (int x = *s0; x < s1; ++x) t = std::max(t, tau_row[x]);
+    *tmax = t;
+  };
+
+  int tilde = Lmax;
+  double coef = 0.0;
+  const int64_t nr_cap = (1ll << 31) - 1;
+  if (plus) {
+    const double delta = o.delta > 0.0 ? o.delta : 1.0 / static_cast<double>(n);
+    // Eq. 13 constant; m counts distinct edges
+    coef = 8.0 * std::log(static_cast<double>(g->d.nslots) / delta) / (eps * eps);
+    HIP_TRY(hipMemsetAsync(g->nr_slot, 0, g->rowptr_h[n] * sizeof(int64_t), st));
+    if (o.tilde_tau >= 0) {
+      tilde = std::min(o.tilde_tau, Lmax);
+    } else {
+      // cost model on sample blocks: dense steps vs. walk steps for each switch point
+      const CostModel cm = cost_model();
+      const double dense_step =
+          cm.step_fixed + static_cast<double>(g->rowptr_h[n]) * B * sizeof(T) / cm.gather_bw;
+      const int nsamp = std::min(nblocks, 4);
+      std::vector<double> cost(Lmax + 1, 0.0);
+      for (int si = 0; si < nsamp; ++si) {
+        const int b = static_cast<int>((si + 0.5) * nblocks / nsamp);
+        int s0, kbeg, kend, tmax;
+        block_range(b, &s0, &kbeg, &kend, &tmax);
+        for (int ell = 2; ell <= Lmax; ++ell) {
+          unsigned long long wk[2] = {0, 0};
+          if (ell < tmax) {
+            rc = R.traverse(s0, kbeg, kend, ell, false, nullptr);
+            if (rc) return rc;
+            HIP_TRY(hipMemsetAsync(g->work, 0, 2 * sizeof(unsigned long long), st));
+            HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, st));
+            HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, ell, gamma, coef, nr_cap,
+                                              R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot,
+                                              g->work, st));
+            HIP_TRY(hipMemcpyAsync(wk, g->work, sizeof(wk), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+          }
+          const int steps = std::min(ell, tmax);
+          cost[ell] += (steps >= 2 ? (steps - 1) * dense_step : 0.0) +
+                       static_cast<double>(wk[1]) * cm.walk_step;
+        }
+      }
+      tilde = Lmax;
+      for (int ell = 2; ell <= Lmax; ++ell)
+        if (cost[ell] < cost[tilde]) tilde = ell;
+      HIP_TRY(hipMemsetAsync(g->nr_slot, 0, g->rowptr_h[n] * sizeof(int64_t), st));
+    }
+    R.stats.tilde_tau = tilde;
+  }
+  HIP_TRY(sc::launch_gacc_init(g->d, g->tau_slot, (plus && tilde < 1) ? 0 : 1, g->gacc, st));
+  R.ev_used = 0;
+  R.stats.prop_launches = 0;
+  R.stats.prop_bytes = 0.0;
+
+  unsigned long long* work = g->work;
+  HIP_TRY(hipMemsetAsync(work, 0, 2 * sizeof(unsigned long long), st));
+  for (int b = 0; b < nblocks; ++b) {
+    int s0, kbeg, kend, tmax;
+    block_range(b, &s0, &kbeg, &kend, &tmax);
+    const int lend = plus ? std::min(tmax, tilde) : tmax;
+    rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc);
+    if (rc) return rc;
+    if (plus && tmax > tilde) {
+      if (tilde < 2) {
+        rc = R.init_low(s0, tilde);
+        if (rc) return rc;
+      }
+      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, st));
+      HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
+                                        R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, work, st));
+      HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
+                                  g->tau_slot, g->nr_slot, g->gacc, st));
+    }
+  }
+  double* out_dev = dev_ptrs ? out_user : g->out_dev;
+  HIP_TRY(sc::launch_combine(g->d, g->gacc, out_dev, st));
+  HIP_TRY(hipEventRecord(t1, st));
+
+  // traces
+  int32_t* tau_o = nullptr;
+  int64_t* nr_o = nullptr;
+  if (o.tau_out) {
+    if (!dev_ptrs && !g->tau_out_dev) HIP_TRY(dev_alloc(&g->tau_out_dev, m));
+    tau_o = dev_ptrs ? o.tau_out : g->tau_out_dev;
+  }
+  if (o.nr_out) {
+    if (!dev_ptrs && !g->nr_out_dev) HIP_TRY(dev_alloc(&g->nr_out_dev, 2 * m));
+    nr_o = dev_ptrs ? o.nr_out : g->nr_out_dev;
+  }
+  HIP_TRY(sc::launch_trace(g->d, g->tau_slot, plus ? g->nr_slot : nullptr, tau_o, nr_o, st));
+  std::vector<int32_t> tilde_h;
+  if (o.tilde_tau_out) {
+    tilde_h.resize(n);
+    for (int64_t x = 0; x < n; ++x) tilde_h[x] = plus ? tilde : tau_row[x];
+    if (dev_ptrs)
+      HIP_TRY(hipMemcpyAsync(o.tilde_tau_out, tilde_h.data(), n * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st));
+    else
+      std::memcpy(o.tilde_tau_out, tilde_h.data(), n * sizeof(int32_t));
+  }
+  unsigned long long wk[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(wk, work, sizeof(wk), hipMemcpyDeviceToHost, st));
+  if (!dev_ptrs) {
+    HIP_TRY(hipMemcpyAsync(out_user, out_dev, m * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (o.tau_out)
+      HIP_TRY(hipMemcpyAsync(o.tau_out, tau_o, m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (o.nr_out)
+      HIP_TRY(hipMemcpyAsync(o.nr_out, nr_o, 2 * m * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  R.stats.total_ms = ms;
+  R.stats.walks = plus ? static_cast<int64_t>(wk[0]) : 0;
+  R.stats.walk_steps = plus ? static_cast<int64_t>(wk[1]) : 0;
+  if (R.timing) {
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < R.ev_used; i += 2) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, g->events[i], g->events[i + 1]));
+      tot += t;
+    }
+    R.stats.prop_ms = tot;
+  }
+  if (st_user) *st_user = R.stats;
+  return SC_OK;
+}
+
+}  // namespace
+
+extern "C" int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double* out,
+                               sc_stats* st) {
+  if (!g) return fail(SC_EINVAL, "graph is NULL");
+  if (!out) return fail(SC_EINVAL, "out is NULL");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(SC_EINVAL, "eps must lie in (0, 1)");
+  if (L < 0) return fail(SC_EINVAL, "L must be >= 0");
+  sc_options opt;
+  if (o)
+    opt = *o;
+  else
+    sc_default_options(&opt);
+  if (opt.method != SC_TGT && opt.method != SC_TGT_PLUS)
+    return fail(SC_EINVAL, "unknown method");
+  if (opt.precision != 0 && opt.precision != 1) return fail(SC_EINVAL, "precision must be 0 or 1");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != g->device) (void)hipSetDevice(g->device);
+  const int rc = opt.precision == 1 ? run_method<double>(g, eps, L, opt, out, st)
+                                    : run_method<float>(g, eps, L, opt, out, st);
+  if (cur != g->device) (void)hipSetDevice(cur);
+  return rc;
+}
+
+extern "C" int sc_all_edges(sc_graph* g, double eps, int L, double* out) {
+  sc_options o;
+  sc_default_options(&o);
+  o.method = L == 0 ? SC_TGT_PLUS : SC_TGT;
+  return sc_all_edges_ex(g, eps, L, &o, out, nullptr);
+}
+
+extern "C" const char* sc_strerror(int code) {
+  switch (code) {
+    case SC_OK: return "ok";
+    case SC_EINVAL: return "invalid argument";
+    case SC_ESELFLOOP: return "self-loop in edge list";
+    case SC_EDUP: return "duplicate edge";
+    case SC_EDISCONNECTED: return "graph is not connected";
+    case SC_EBIPARTITE: return "graph is bipartite";
+    case SC_ENOMEM: return "out of memory";
+    case SC_EHIP: return "HIP runtime error";
+    case SC_ENOTIMPL: return "not implemented";
+    default: return "unknown error code";
+  }
+}
+
+extern "C" const char* sc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* sc_version(void) { return "sc-mi355x 0.1 (gfx950)"; }

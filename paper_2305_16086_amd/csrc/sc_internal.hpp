@@ -1,0 +1,136 @@
+// Internal declarations shared by the host orchestration and the kernel
+// translation units of libsc.  Not part of the public ABI (see include/sc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sc.h"
+
+namespace sc {
+
+// Rows of the CSR are cut into "tasks" of at most kChunk slots.  A row with
+// more slots than kChunk is split into several tasks whose partial sums are
+// combined by a fix-up pass in a fixed order (deterministic, no atomics).
+constexpr int kChunk = 256;
+constexpr int kWavesPerBlock = 4;     // 256-thread workgroups
+constexpr int kMaxGamma = 16;         // candidate lists kept in registers
+
+struct Task {
+  int32_t row;
+  int32_t beg;      // first CSR slot
+  int32_t end;      // one past the last CSR slot
+  int32_t part;     // -1: whole row; else index of this chunk's partial-sum row
+};
+
+struct HeavyRow {
+  int32_t row;
+  int32_t part0;    // first partial row
+  int32_t nparts;   // number of chunks
+  int32_t pad;
+};
+
+// Per-column summary of q = p_tilde(., s_c) used by Algorithm 3 / Lemma 4.3.
+struct ColStats {
+  double maxV, minV;     // max / min over all nodes
+  double rho;            // upper bound on rho_i (Eq. 16), safe reading of Alg. 3
+  double maxN, minN;     // max / min over N(s_c)
+};
+
+struct DeviceGraph {
+  int32_t n = 0;
+  int64_t m = 0;                 // input edges (halves 0..2m-1)
+  int64_t nslots = 0;            // CSR slots (2 x distinct edges)
+  int32_t* rowptr = nullptr;     // [n+1]
+  int32_t* col = nullptr;        // [2m] neighbours, ascending per row
+  int32_t* deg = nullptr;        // [n]
+  int32_t* slot_row = nullptr;   // [2m] row of each slot
+  int32_t* slot_half = nullptr;  // [2m] slot -> half id (e, or e + m for (v_e -> u_e))
+  int32_t* half_slot = nullptr;  // [2m] half id -> slot
+  float* inv_deg_f = nullptr;    // [n]
+  double* inv_deg_d = nullptr;   // [n]
+  Task* tasks = nullptr;         // [ntasks] heavy chunks first, then whole rows
+  int32_t ntasks = 0;
+  HeavyRow* heavy = nullptr;     // [nheavy]
+  int32_t nheavy = 0;
+  int32_t nparts = 0;            // total partial rows
+};
+
+// --------------------------------------------------------------- kernels (launch wrappers)
+// All wrappers enqueue on `st` and return the hipError_t of the launch.
+
+// gacc[k] = 1/d_s - [tau_k >= 1] * 1/(d_s d_j): the l = 0 and l = 1 terms of
+// Eq. 9, whose probabilities are known in closed form (p_0 = e_s,
+// p_1(s,s) = 0, p_1(j,s) = 1/d_j).
+// include_l1 = 0 leaves the l = 1 term to the walk tail (TGT+ with tilde_tau = 0).
+hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int include_l1,
+                            double* gacc, hipStream_t st);
+
+// tau per slot: uniform L (odd) when L > 0, else the lambda* bound of
+// Theorem 3.2 with Upsilon = Delta = 0.  Also the per-row maximum.
+hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
+                      int32_t* tau_slot, int32_t* tau_row, hipStream_t st);
+
+// Source block [s0, s0+B): mark bit c of mask[u] for every u in N(s0+c).
+hipError_t launch_mask_set(const DeviceGraph& g, int s0, int B, unsigned long long* mask,
+                           bool clear, hipStream_t st);
+
+// Y2 = P P Y0 for the indicator block via the neighbour masks.
+template <typename T>
+hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask, T* Y,
+                         T* partials, hipStream_t st);
+
+// Yn = P Yp (dense block gather), chunked rows write partial sums.
+template <typename T>
+hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
+                            hipStream_t st);
+
+// Heavy rows: Y[row] = inv_deg[row] * sum of partials, in chunk order.
+template <typename T>
+hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
+
+// gacc[k] += (Y[s][c] - Y[j][c]) / d_s for the block's slots with l <= tau_k.
+template <typename T>
+hipError_t launch_accumulate(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
+                             const T* Y, const int32_t* tau_slot, double* gacc, hipStream_t st);
+
+// Algorithm 3 summary per column of the block (top-gamma, rho bound, extremes).
+template <typename T>
+hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
+                           ColStats* cs, hipStream_t st);
+
+// n_r per slot (Eq. 13 with chi of Eq. 17 / Eq. 15); 0 where tau_k <= tilde.
+template <typename T>
+hipError_t launch_walk_counts(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
+                              int gamma,
+                              double coef, int64_t nr_cap, const T* Y, const ColStats* cs,
+                              const int32_t* tau_slot, int64_t* nr_slot,
+                              unsigned long long* work /*[2]: walks, steps*/, hipStream_t st);
+
+// Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots.
+template <typename T>
+hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
+                        uint64_t seed,
+                        const T* Y, const int32_t* tau_slot, const int64_t* nr_slot,
+                        double* gacc, hipStream_t st);
+
+// out[e] = gacc[slot(u_e->v_e)] + gacc[slot(v_e->u_e)] (Algorithm 2 line 12).
+hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,
+                          hipStream_t st);
+
+// Trace outputs in input order.
+hipError_t launch_trace(const DeviceGraph& g, const int32_t* tau_slot, const int64_t* nr_slot,
+                        int32_t* tau_out, int64_t* nr_out, hipStream_t st);
+
+// --------------------------------------------------------------- Lanczos helpers
+hipError_t launch_nmat_spmv(const DeviceGraph& g, const double* sid, const double* x,
+                            double* y, hipStream_t st);
+hipError_t launch_multi_dot(const double* V, int ncols, int64_t ld, const double* w,
+                            int64_t n, double* out, hipStream_t st);
+hipError_t launch_multi_axpy(const double* V, int ncols, int64_t ld, const double* h,
+                             double* w, int64_t n, hipStream_t st);
+
+}  // namespace sc

@@ -1,0 +1,251 @@
+"""ctypes binding of libsc (include/sc.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Host arrays
+are numpy; device buffers are torch CUDA tensors (PyTorch is used only for
+device memory and streams).  If ``libsc.so`` has not been built the import
+fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsc.so")
+
+SC_OK = 0
+SC_EINVAL = -1
+SC_ESELFLOOP = -2
+SC_EDUP = -3
+SC_EDISCONNECTED = -4
+SC_EBIPARTITE = -5
+SC_ENOMEM = -6
+SC_EHIP = -7
+SC_ENOTIMPL = -8
+
+SC_MERGE_DUPS = 0x2
+SC_DEVICE_PTRS = 0x1
+SC_TIME_KERNELS = 0x4
+
+SC_TGT = 0
+SC_TGT_PLUS = 1
+
+
+class ScOptions(C.Structure):
+    _fields_ = [
+        ("method", C.c_int),
+        ("precision", C.c_int),
+        ("block", C.c_int),
+        ("gamma", C.c_int),
+        ("delta", C.c_double),
+        ("seed", C.c_uint64),
+        ("tilde_tau", C.c_int),
+        ("max_L", C.c_int),
+        ("lambda_star", C.c_double),
+        ("flags", C.c_uint),
+        ("stream", C.c_void_p),
+        ("tau_out", C.c_void_p),
+        ("tilde_tau_out", C.c_void_p),
+        ("nr_out", C.c_void_p),
+    ]
+
+
+class ScStats(C.Structure):
+    _fields_ = [
+        ("L_used", C.c_int),
+        ("L_min", C.c_int),
+        ("tilde_tau", C.c_int),
+        ("block", C.c_int),
+        ("lambda_star", C.c_double),
+        ("walks", C.c_int64),
+        ("walk_steps", C.c_int64),
+        ("prop_launches", C.c_int64),
+        ("prop_ms", C.c_double),
+        ("prop_bytes", C.c_double),
+        ("total_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ScError(RuntimeError):
+    def __init__(self, code, where, text):
+        super().__init__(f"{where}: {text} (code {code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsc.so not built at {LIB_PATH}; run python -m paper_2305_16086_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    lib.sc_default_options.argtypes = [C.POINTER(ScOptions)]
+    lib.sc_default_options.restype = None
+    lib.sc_build_graph.argtypes = [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint,
+                                   C.POINTER(C.c_void_p)]
+    lib.sc_build_graph.restype = C.c_int
+    lib.sc_graph_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sc_graph_size.restype = C.c_int
+    lib.sc_free_graph.argtypes = [C.c_void_p]
+    lib.sc_free_graph.restype = None
+    lib.sc_lambda_star.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+    lib.sc_lambda_star.restype = C.c_int
+    lib.sc_all_edges.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_void_p]
+    lib.sc_all_edges.restype = C.c_int
+    lib.sc_all_edges_ex.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(ScOptions),
+                                    C.c_void_p, C.POINTER(ScStats)]
+    lib.sc_all_edges_ex.restype = C.c_int
+    lib.sc_strerror.argtypes = [C.c_int]
+    lib.sc_strerror.restype = C.c_char_p
+    lib.sc_last_error.argtypes = []
+    lib.sc_last_error.restype = C.c_char_p
+    lib.sc_version.argtypes = []
+    lib.sc_version.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+# names declared in include/sc.h, for the export check
+EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_graph",
+            "sc_lambda_star", "sc_all_edges", "sc_all_edges_ex", "sc_strerror",
+            "sc_last_error", "sc_version"]
+
+
+def _check(rc, where):
+    if rc != SC_OK:
+        raise ScError(rc, where, _lib.sc_last_error().decode())
+
+
+def lib():
+    return _lib
+
+
+def sc_version() -> str:
+    return _lib.sc_version().decode()
+
+
+def sc_strerror(code: int) -> str:
+    return _lib.sc_strerror(code).decode()
+
+
+def sc_last_error() -> str:
+    return _lib.sc_last_error().decode()
+
+
+def sc_default_options(**kw) -> ScOptions:
+    o = ScOptions()
+    _lib.sc_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Graph:
+    """Owning wrapper of an sc_graph handle."""
+
+    def __init__(self, handle, n, m):
+        self._h = handle
+        self.n = n
+        self.m = m
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph already freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            _lib.sc_free_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sc_build_graph(n, u, v, flags: int = 0) -> Graph:
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    if u.shape != v.shape or u.ndim != 1:
+        raise ValueError("u and v must be 1-D arrays of equal length")
+    h = C.c_void_p()
+    rc = _lib.sc_build_graph(int(n), len(u), u.ctypes.data, v.ctypes.data, int(flags), C.byref(h))
+    _check(rc, "sc_build_graph")
+    return Graph(h, int(n), len(u))
+
+
+def sc_graph_size(g: Graph):
+    n = C.c_int64()
+    m = C.c_int64()
+    _check(_lib.sc_graph_size(g.handle, C.byref(n), C.byref(m)), "sc_graph_size")
+    return n.value, m.value
+
+
+def sc_lambda_star(g: Graph) -> float:
+    lam = C.c_double()
+    _check(_lib.sc_lambda_star(g.handle, C.byref(lam)), "sc_lambda_star")
+    return lam.value
+
+
+def sc_all_edges(g: Graph, eps: float, L: int, out=None) -> np.ndarray:
+    if out is None:
+        out = np.empty(g.m, dtype=np.float64)
+    if out.dtype != np.float64 or not out.flags.c_contiguous or out.shape != (g.m,):
+        raise ValueError("out must be a contiguous float64 array of length m")
+    _check(_lib.sc_all_edges(g.handle, float(eps), int(L), out.ctypes.data), "sc_all_edges")
+    return out
+
+
+def _ptr(x):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()  # torch tensor
+
+
+def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = None, out=None,
+                    tau_out=None, tilde_tau_out=None, nr_out=None):
+    """Run with explicit options.  ``out`` and the trace arrays are numpy arrays
+    (host) or torch CUDA tensors (then SC_DEVICE_PTRS is set and the current
+    torch stream is used unless options.stream is set).  Returns (out, stats dict)."""
+    o = options if options is not None else sc_default_options()
+    device = out is not None and not isinstance(out, np.ndarray)
+    if out is None:
+        out = np.empty(g.m, dtype=np.float64)
+    if device:
+        import torch
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != g.m:
+            raise ValueError("device out must be a CUDA float64 tensor of length m")
+        o.flags |= SC_DEVICE_PTRS
+        if not o.stream:
+            o.stream = torch.cuda.current_stream(out.device).cuda_stream
+    else:
+        if out.dtype != np.float64 or out.shape != (g.m,) or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous float64 array of length m")
+        o.flags &= ~SC_DEVICE_PTRS
+    for arr, name, n_exp, dt in ((tau_out, "tau_out", g.m, "int32"),
+                                 (tilde_tau_out, "tilde_tau_out", g.n, "int32"),
+                                 (nr_out, "nr_out", 2 * g.m, "int64")):
+        if arr is None:
+            continue
+        if device == isinstance(arr, np.ndarray):
+            raise ValueError(f"{name} must be on the same side (host/device) as out")
+        if (arr.numel() if device else arr.size) != n_exp or str(arr.dtype).split(".")[-1] != dt:
+            raise ValueError(f"{name} must hold {n_exp} {dt}")
+    o.tau_out = _ptr(tau_out)
+    o.tilde_tau_out = _ptr(tilde_tau_out)
+    o.nr_out = _ptr(nr_out)
+    st = ScStats()
+    rc = _lib.sc_all_edges_ex(g.handle, float(eps), int(L), C.byref(o), _ptr(out), C.byref(st))
+    _check(rc, "sc_all_edges_ex")
+    return out, st.as_dict()

@@ -1,0 +1,72 @@
+"""Host-side checks of the C-ABI library that need no GPU: the shared library
+loads, exports every entry point include/sc.h declares, and the graph
+validation rejects what the paper's definitions exclude (these checks run
+before any device call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "sc.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", hdr)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2305_16086_amd import sc
+    lib = ctypes.CDLL(sc.LIB_PATH)
+    names = declared_symbols()
+    assert "sc_build_graph" in names and "sc_all_edges" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(sc.EXPORTED) == names
+
+
+def test_version_and_error_texts():
+    from paper_2305_16086_amd import sc
+    assert "gfx950" in sc.sc_version()
+    for code in range(0, -9, -1):
+        assert sc.sc_strerror(code) and sc.sc_strerror(code) != "unknown error code"
+    assert sc.sc_strerror(-99) == "unknown error code"
+
+
+def _code(n, u, v, flags=0):
+    from paper_2305_16086_amd import sc
+    with pytest.raises(sc.ScError) as ei:
+        sc.sc_build_graph(n, u, v, flags)
+    return ei.value.code
+
+
+def test_validation_rejects_invalid_graphs():
+    from paper_2305_16086_amd import sc
+    assert _code(3, [0, 1, 2], [1, 2, 2]) == sc.SC_ESELFLOOP
+    assert _code(3, [0, 1, 0, 1], [1, 2, 2, 0]) == sc.SC_EDUP
+    assert _code(3, [0, 1, 0], [1, 2, 3]) == sc.SC_EINVAL
+    assert _code(3, [0, 1, -1], [1, 2, 2]) == sc.SC_EINVAL
+    assert _code(1, [0], [0]) == sc.SC_EINVAL
+    assert _code(6, [0, 1, 0, 3, 4, 3], [1, 2, 2, 4, 5, 5]) == sc.SC_EDISCONNECTED
+    n, u, v = gg.cycle_graph(6)
+    assert _code(n, u, v) == sc.SC_EBIPARTITE
+    n, u, v = gg.king_grid(2)   # a single edge
+    assert _code(n, u, v) == sc.SC_EBIPARTITE
+    assert "bipartite" in sc.sc_last_error()
+
+
+def test_validation_of_even_cycle_plus_chord_is_not_bipartite_error():
+    from paper_2305_16086_amd import sc
+    # C6 plus a chord (0, 2) has a triangle; validation must not call it bipartite.
+    n, u, v = gg.cycle_graph(6)
+    u = np.append(u, 0)
+    v = np.append(v, 2)
+    try:
+        sc.sc_build_graph(n, u, v)
+    except sc.ScError as e:       # without a GPU the device upload fails after validation
+        assert e.code in (sc.SC_EHIP, sc.SC_ENOMEM)
