@@ -58,8 +58,10 @@ enum {
 /* methods (sc_options.method) */
 #define SC_TGT 0       /* Algorithm 2: traversal to tau for every source */
 #define SC_TGT_PLUS 1  /* Algorithm 4: traversal to tilde_tau, then random walks */
+#define SC_LEARNED 2   /* learned tail closure after L0 = 8 steps, TGT as fallback */
 
 typedef struct sc_graph sc_graph;   /* opaque: device CSR, maps, work buffers */
+typedef struct sc_mlp sc_mlp;       /* opaque: tail-closure network on the device */
 
 typedef struct sc_options {
   int method;          /* SC_TGT or SC_TGT_PLUS                                      */
@@ -78,6 +80,10 @@ typedef struct sc_options {
   int32_t* tilde_tau_out;  /* [n]  switch step per source node (TGT: tau_p)          */
   int64_t* nr_out;         /* [2m] walk pairs per half-edge: [0,m) = (u_e -> v_e),
                                    [m,2m) = (v_e -> u_e)                            */
+  /* SC_LEARNED only */
+  const sc_mlp* mlp;       /* trained network (required)                              */
+  int infer_bf16;          /* 1: BF16 MFMA inference (default), 0: FP32               */
+  int force_fallback;      /* 1: every edge takes the fallback traversal              */
 } sc_options;
 
 typedef struct sc_stats {
@@ -92,6 +98,7 @@ typedef struct sc_stats {
   double prop_ms;          /* sum of propagation launch times (SC_TIME_KERNELS)       */
   double prop_bytes;       /* algorithmic bytes of all propagation launches           */
   double total_ms;         /* wall time of the call on the stream                     */
+  int64_t fallback_edges;  /* SC_LEARNED: edges computed by the fallback traversal    */
 } sc_stats;
 
 /* Fill *o with defaults: TGT, FP32, gamma 10, delta 1/n, seed 0x5C5C, auto tilde_tau. */
@@ -151,6 +158,67 @@ int sc_all_edges(sc_graph* g, double eps, int L, double* out);
  */
 int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double* out,
                     sc_stats* st);
+
+/* ------------------------------------------------------------------ learned closure
+ *
+ * Not in the paper: an optional form that stops the traversal after L0 = 8
+ * steps, truncates at the odd tau0 = 7 and predicts the remaining tail.  The
+ * series terms of Eq. 2 have the spectral form of Eq. 18 with non-negative
+ * weights, so the pair sums u_k = t_2k + t_2k+1 are a non-negative mixture of
+ * geometric sequences; hence the tail lies in [u3 r/(1-r), u3 l2/(1-l2)] with
+ * r = u3/u2 and l2 = lambda*^2.  The network (16 -> 64 -> 64 -> 1, silu)
+ * predicts z = tail/u3 and the prediction is clamped to that interval, so the
+ * error of every edge is at most u3 (hi - lo); edges where that exceeds eps,
+ * or whose features leave the training range, are recomputed by TGT with the
+ * truncation of Theorem 3.2.  Arrays named X, z, w, y below are DEVICE
+ * pointers: X is row-major [N][16] float, z, w, y are [N] float.
+ */
+typedef struct sc_train_options {
+  int epochs;          /* passes over the data (default 20)            */
+  int batch;           /* samples per Adam step (default 4096)         */
+  float lr;            /* Adam step size (default 2e-3)                */
+  uint64_t seed;       /* shuffling seed                               */
+  void* stream;        /* hipStream_t, NULL = null stream             */
+} sc_train_options;
+
+void sc_default_train_options(sc_train_options* t);
+
+/* New network with seeded fan-in-scaled uniform weights and zero biases. */
+int sc_mlp_create(uint64_t seed, sc_mlp** out);
+void sc_mlp_free(sc_mlp* net);
+
+/* Copy parameters (5313 floats: W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[64], b3), feature normalisation (32 floats: mean[16], 1/std[16]) and
+ * feature range (32 floats: min[16], max[16]) to / from host memory; any
+ * pointer may be NULL.  Setting a range enables the out-of-range fallback. */
+int sc_mlp_get(const sc_mlp* net, float* params, float* norm, float* range);
+int sc_mlp_set(sc_mlp* net, const float* params, const float* norm, const float* range);
+
+/* Training data of one graph: features X [m][16] (from the first 8 steps),
+ * targets z = (s_Lref - s_7)/u3 and weights w (0 where u3 = 0), with s_Lref
+ * from TGT at the uniform odd truncation L_ref (e.g. 201).  Device pointers. */
+int sc_closure_dataset(sc_graph* g, int L_ref, int precision, float* X, float* z, float* w,
+                       void* stream);
+
+/* Features and certified interval of every edge (device pointers; any of the
+ * double arrays may be NULL): s0 = s_7, uK = u3, [lo, hi] as above. */
+int sc_closure_features(sc_graph* g, int precision, float* X, double* s0, double* uK,
+                        double* lo, double* hi, void* stream);
+
+/* Mean squared error training with Adam on N samples; the first call fits the
+ * normalisation and the feature range on X.  loss_per_epoch (host, may be
+ * NULL) receives the mean weighted loss of every epoch. */
+int sc_mlp_train(sc_mlp* net, const float* X, const float* z, const float* w, int64_t N,
+                 const sc_train_options* t, float* loss_per_epoch);
+
+/* Gradient of the mean weighted squared error over all N samples (host
+ * outputs: grad[5313], loss[1]); the normalisation in use is applied. */
+int sc_mlp_grad(sc_mlp* net, const float* X, const float* z, const float* w, int64_t N,
+                float* grad_host, float* loss_host, void* stream);
+
+/* y = network(X) for N samples, BF16 MFMA (bf16 = 1) or FP32 (bf16 = 0). */
+int sc_mlp_predict(const sc_mlp* net, const float* X, int64_t N, int bf16, float* y,
+                   void* stream);
 
 /* Text for an error code; never NULL. */
 const char* sc_strerror(int code);

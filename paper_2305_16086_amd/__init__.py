@@ -6,6 +6,7 @@ ctypes binding.
 """
 from .sc import (  # noqa: F401
     SC_DEVICE_PTRS,
+    SC_LEARNED,
     SC_MERGE_DUPS,
     SC_TGT,
     SC_TGT_PLUS,
@@ -21,4 +22,15 @@ from .sc import (  # noqa: F401
     sc_last_error,
     sc_strerror,
     sc_version,
+    Mlp,
+    sc_closure_dataset,
+    sc_closure_features,
+    sc_default_train_options,
+    sc_mlp_create,
+    sc_mlp_free,
+    sc_mlp_get,
+    sc_mlp_grad,
+    sc_mlp_predict,
+    sc_mlp_set,
+    sc_mlp_train,
 )

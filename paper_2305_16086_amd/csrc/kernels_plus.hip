@@ -40,25 +40,163 @@ __device__ inline bool adjacent(const int32_t* __restrict__ rowptr, const int32_
   return false;
 }
 
-// One workgroup per source column c of the block.
+
+// Insert (v, id) into a list kept in (value desc, id asc) order; the last
+// entry falls off.  Fully unrolled so the list stays in registers.
+__device__ inline void list_insert(double (&lv)[kMaxGamma], int (&li)[kMaxGamma], int gamma,
+                                   double v, int id) {
+  double cv = v;
+  int ci = id;
+#pragma unroll
+  for (int p = 0; p < kMaxGamma; ++p) {
+    if (p < gamma && ranks_before(cv, ci, lv[p], li[p])) {
+      const double tv = lv[p];
+      const int ti = li[p];
+      lv[p] = cv;
+      li[p] = ci;
+      cv = tv;
+      ci = ti;
+    }
+  }
+}
+
+__device__ inline void list_last(const double (&lv)[kMaxGamma], const int (&li)[kMaxGamma],
+                                 int gamma, double* v, int* id) {
+#pragma unroll
+  for (int p = 0; p < kMaxGamma; ++p)
+    if (p == gamma - 1) {
+      *v = lv[p];
+      *id = li[p];
+    }
+}
+
+// The per-column summary of Algorithm 3 runs in four passes over the block
+// state Y (lanes are columns, rows are cut into kColParts chunks):
+//  A  chunk maxima and minima (one coalesced read of Y);
+//  B  per column: overall extremes and theta = the gamma-th largest chunk
+//     maximum.  The gamma largest chunk maxima are gamma distinct entries, so
+//     every entry of the column's top-gamma list is >= theta;
+//  C  chunks whose maximum reaches theta keep their top-gamma entries >= theta
+//     and register themselves with the column;
+//  D  per column: merge the registered lists, test candidate pairs for edges
+//     (Algorithm 3 lines 3-5, safe reading), extremes over N(s).
+// Partial p of column c: pmx/pmn[p*B + c], lists pv/pi[(p*B + c)*gamma + r].
+
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_colstats(int n, int s0, int gamma,
-                                                  const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const T* __restrict__ Y,
-                                                  ColStats* __restrict__ cs) {
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  __shared__ int so[256];
-  __shared__ double top_v[kMaxGamma];
-  __shared__ int top_i[kMaxGamma];
-  __shared__ double red_a[256];
-  __shared__ double red_b[256];
+__global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part,
+                                                     const T* __restrict__ Y,
+                                                     T* __restrict__ pmx, T* __restrict__ pmn) {
+  constexpr int G = 64 / B;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int c = lane % B;
+  const int part = wave * G + lane / B;
+  const int x0 = part * rows_per_part;
+  const int x1 = min(n, x0 + rows_per_part);
+  T mx = T(-1), mn = T(2);   // probabilities lie in [0, 1]: -1 / 2 mark an empty chunk
+  for (int xb = x0; xb < x1; xb += 8) {
+    T q[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      q[r] = (xb + r < x1) ? Y[static_cast<size_t>(xb + r) * B + c] : T(-1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (xb + r < x1) {
+        mx = q[r] > mx ? q[r] : mx;
+        mn = q[r] < mn ? q[r] : mn;
+      }
+    }
+  }
+  const size_t o = static_cast<size_t>(part) * B + c;
+  pmx[o] = mx;
+  pmn[o] = mn;
+}
 
+// one wave per column
+template <typename T, int B>
+__global__ __launch_bounds__(64) void k_colthresh(int gamma, int nparts, const T* __restrict__ pmx,
+                                                  const T* __restrict__ pmn, T* __restrict__ thr,
+                                                  int* __restrict__ nact, ColStats* __restrict__ cs) {
+  constexpr int kPer = kColParts / 64;
   const int c = blockIdx.x;
-  const int s = s0 + c;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
+  double v[kPer];
+  double mx = -DBL_MAX, mn = DBL_MAX;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int p = lane + 64 * k;
+    const size_t o = static_cast<size_t>(p) * B + c;
+    v[k] = p < nparts ? static_cast<double>(pmx[o]) : -1.0;
+    if (v[k] >= 0.0) {
+      mx = fmax(mx, v[k]);
+      mn = fmin(mn, static_cast<double>(pmn[o]));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+  }
+  // gamma rounds: remove the largest remaining chunk maximum
+  double theta = -1.0;
+  for (int r = 0; r < gamma; ++r) {
+    double best = -1.0;
+    int at = -1;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (v[k] > best) {
+        best = v[k];
+        at = k;
+      }
+    double wbest = best;
+    int wlane = lane;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(wbest, off, 64);
+      const int ol = __shfl_xor(wlane, off, 64);
+      if (ob > wbest || (ob == wbest && ol < wlane)) {
+        wbest = ob;
+        wlane = ol;
+      }
+    }
+    if (wbest < 0.0) {   // fewer than gamma non-empty chunks: keep every entry
+      theta = -1.0;
+      break;
+    }
+    theta = wbest;
+    if (lane == wlane) {
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        if (k == at) v[k] = -1.0;
+    }
+  }
+  if (lane == 0) {
+    thr[c] = static_cast<T>(theta);
+    nact[c] = 0;
+    cs[c].maxV = mx;
+    cs[c].minV = mn;
+  }
+}
 
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_colscan(int n, int rows_per_part, int gamma,
+                                                      const T* __restrict__ Y,
+                                                      const T* __restrict__ pmx,
+                                                      const T* __restrict__ thr,
+                                                      T* __restrict__ pv, int* __restrict__ pi,
+                                                      int* __restrict__ nact,
+                                                      int* __restrict__ act) {
+  constexpr int G = 64 / B;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int c = lane % B;
+  const int part = wave * G + lane / B;
+  const size_t o = static_cast<size_t>(part) * B + c;
+  const T th = thr[c];
+  const bool mine = pmx[o] >= th && pmx[o] >= T(0);
+  if (__ballot(mine) == 0ull) return;   // whole wave uniform
+  const int x0 = part * rows_per_part;
+  const int x1 = mine ? min(n, x0 + rows_per_part) : x0;
   double lv[kMaxGamma];
   int li[kMaxGamma];
 #pragma unroll
@@ -66,50 +204,90 @@ __global__ __launch_bounds__(256) void k_colstats(int n, int s0, int gamma,
     lv[p] = -DBL_MAX;
     li[p] = INT_MAX;
   }
-  double last = -DBL_MAX;   // value at position gamma-1 of this thread's list
-  double mx = -DBL_MAX, mn = DBL_MAX;
-  for (int x = tid; x < n; x += 256) {
-    const double q = static_cast<double>(Y[static_cast<size_t>(x) * B + c]);
-    mx = fmax(mx, q);
-    mn = fmin(mn, q);
-    if (gamma > 0 && q > last) {
-      // ids increase along this thread's scan, so an equal value never outranks
-      double cv = q;
-      int ci = x;
+  double last = -DBL_MAX;
+  for (int xb = x0; xb < x1; xb += 8) {
+    T q[8];
 #pragma unroll
-      for (int p = 0; p < kMaxGamma; ++p) {
-        if (p < gamma && ranks_before(cv, ci, lv[p], li[p])) {
-          const double tv = lv[p];
-          const int ti = li[p];
-          lv[p] = cv;
-          li[p] = ci;
-          cv = tv;
-          ci = ti;
-        }
+    for (int r = 0; r < 8; ++r)
+      q[r] = (xb + r < x1) ? Y[static_cast<size_t>(xb + r) * B + c] : T(-1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double v = static_cast<double>(q[r]);
+      // ids increase along the scan: only a strictly larger value outranks the tail
+      if (xb + r < x1 && q[r] >= th && v > last) {
+        list_insert(lv, li, gamma, v, xb + r);
+        int dummy;
+        list_last(lv, li, gamma, &last, &dummy);
       }
+    }
+  }
+  if (mine) {
 #pragma unroll
-      for (int p = 0; p < kMaxGamma; ++p)
-        if (p == gamma - 1) last = lv[p];
+    for (int p = 0; p < kMaxGamma; ++p) {
+      if (p < gamma) {
+        pv[o * gamma + p] = static_cast<T>(lv[p]);
+        pi[o * gamma + p] = li[p];
+      }
+    }
+    const int k = atomicAdd(&nact[c], 1);
+    act[static_cast<size_t>(c) * kColParts + k] = part;
+  }
+}
+
+__device__ inline void wave_best(double& v, int& id, int& owner) {
+  // (value desc, id asc) arg-best over the wave, fixed butterfly
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(id, off, 64);
+    const int oo = __shfl_xor(owner, off, 64);
+    if (ranks_before(ov, oi, v, id)) {
+      v = ov;
+      id = oi;
+      owner = oo;
     }
   }
+}
 
-  // extremes over V
-  red_a[tid] = mx;
-  red_b[tid] = mn;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) {
-      red_a[tid] = fmax(red_a[tid], red_a[tid + w]);
-      red_b[tid] = fmin(red_b[tid], red_b[tid + w]);
-    }
-    __syncthreads();
+// one wave per column; the registered chunk order is arbitrary but the
+// selection uses the total order (value desc, id asc), so the result is not
+template <typename T, int B>
+__global__ __launch_bounds__(64) void k_colmerge(int n, int s0, int gamma,
+                                                 const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const T* __restrict__ Y,
+                                                 const T* __restrict__ pv,
+                                                 const int* __restrict__ pi,
+                                                 const int* __restrict__ nact,
+                                                 const int* __restrict__ act,
+                                                 ColStats* __restrict__ cs) {
+  const int c = blockIdx.x;
+  const int s = s0 + c;
+  const int lane = threadIdx.x;
+  double lv[kMaxGamma];
+  int li[kMaxGamma];
+#pragma unroll
+  for (int p = 0; p < kMaxGamma; ++p) {
+    lv[p] = -DBL_MAX;
+    li[p] = INT_MAX;
   }
-  const double maxV = red_a[0];
-  const double minV = red_b[0];
-  __syncthreads();
-
-  // merge the per-thread candidate lists: gamma rounds of a workgroup argmax
+  double lastv = -DBL_MAX;
+  int lasti = INT_MAX;
+  const int na = nact[c];
+  for (int k = lane; k < na; k += 64) {
+    const size_t o = static_cast<size_t>(act[static_cast<size_t>(c) * kColParts + k]) * B + c;
+    for (int r = 0; r < gamma; ++r) {
+      const int id = pi[o * gamma + r];
+      if (id == INT_MAX) break;
+      const double v = static_cast<double>(pv[o * gamma + r]);
+      if (!ranks_before(v, id, lastv, lasti)) break;   // partial lists are sorted
+      list_insert(lv, li, gamma, v, id);
+      list_last(lv, li, gamma, &lastv, &lasti);
+    }
+  }
   const int cnt = gamma < n ? gamma : n;
+  double top_v = -DBL_MAX;   // lane r keeps the r-th candidate
+  int top_i = INT_MAX;
   int head = 0;
   for (int r = 0; r < cnt; ++r) {
     double hv = -DBL_MAX;
@@ -120,63 +298,44 @@ __global__ __launch_bounds__(256) void k_colstats(int n, int s0, int gamma,
         hv = lv[p];
         hi = li[p];
       }
-    sv[tid] = hv;
-    si[tid] = hi;
-    so[tid] = tid;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if (tid < w && ranks_before(sv[tid + w], si[tid + w], sv[tid], si[tid])) {
-        sv[tid] = sv[tid + w];
-        si[tid] = si[tid + w];
-        so[tid] = so[tid + w];
-      }
-      __syncthreads();
+    int owner = lane;
+    wave_best(hv, hi, owner);
+    if (lane == r) {
+      top_v = hv;
+      top_i = hi;
     }
-    if (tid == 0) {
-      top_v[r] = sv[0];
-      top_i[r] = si[0];
-    }
-    if (so[0] == tid) ++head;
-    __syncthreads();
+    if (owner == lane) ++head;
   }
-
-  // rho bound: best candidate-pair edge, and q[c1] + q[c_gamma] for edges
-  // leaving the candidate set (Algorithm 3 lines 3-5, safe reading)
   double best = -DBL_MAX;
   if (gamma > 0) {
-    for (int p = tid; p < cnt * cnt; p += 256) {
-      const int a = p / cnt, b = p % cnt;
-      if (a < b && adjacent(rowptr, col, top_i[a], top_i[b])) best = fmax(best, top_v[a] + top_v[b]);
+    for (int p = 0; p < cnt * cnt; p += 64) {
+      const int q = p + lane;
+      const int a = q / cnt, b = q % cnt;
+      const int ia = __shfl(top_i, a < 64 ? a : 0, 64);
+      const int ib = __shfl(top_i, b < 64 ? b : 0, 64);
+      const double va = __shfl(top_v, a < 64 ? a : 0, 64);
+      const double vb = __shfl(top_v, b < 64 ? b : 0, 64);
+      if (q < cnt * cnt && a < b && adjacent(rowptr, col, ia, ib)) best = fmax(best, va + vb);
     }
   }
-  // extremes over N(s)
   double nmx = -DBL_MAX, nmn = DBL_MAX;
-  for (int k = rowptr[s] + tid; k < rowptr[s + 1]; k += 256) {
+  for (int k = rowptr[s] + lane; k < rowptr[s + 1]; k += 64) {
     const double q = static_cast<double>(Y[static_cast<size_t>(col[k]) * B + c]);
     nmx = fmax(nmx, q);
     nmn = fmin(nmn, q);
   }
-  __syncthreads();
-  red_a[tid] = nmx;
-  red_b[tid] = nmn;
-  sv[tid] = best;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) {
-      red_a[tid] = fmax(red_a[tid], red_a[tid + w]);
-      red_b[tid] = fmin(red_b[tid], red_b[tid + w]);
-      sv[tid] = fmax(sv[tid], sv[tid + w]);
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    best = fmax(best, __shfl_xor(best, off, 64));
+    nmx = fmax(nmx, __shfl_xor(nmx, off, 64));
+    nmn = fmin(nmn, __shfl_xor(nmn, off, 64));
   }
-  if (tid == 0) {
-    ColStats o;
-    o.maxV = maxV;
-    o.minV = minV;
-    o.rho = gamma > 0 ? fmax(sv[0], top_v[0] + top_v[cnt - 1]) : 0.0;
-    o.maxN = red_a[0];
-    o.minN = red_b[0];
-    cs[c] = o;
+  const double first = __shfl(top_v, 0, 64);
+  const double lastc = __shfl(top_v, cnt > 0 ? cnt - 1 : 0, 64);
+  if (lane == 0) {
+    cs[c].rho = gamma > 0 ? fmax(best, first + lastc) : 0.0;
+    cs[c].maxN = nmx;
+    cs[c].minN = nmn;
   }
 }
 
@@ -302,13 +461,41 @@ __global__ __launch_bounds__(kThreads) void k_walks(
 
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
-                           ColStats* cs, hipStream_t st) {
+                           ColStats* cs, void* scratch, hipStream_t st) {
   int ncols = B;
   if (s0 + ncols > g.n) ncols = g.n - s0;
   if (ncols <= 0) return hipSuccess;
-  if (gamma > kMaxGamma) return hipErrorInvalidValue;
-  SC_DISPATCH_B(B, (k_colstats<T, kB><<<ncols, 256, 0, st>>>(g.n, s0, gamma, g.rowptr, g.col, Y,
+  if (gamma > kMaxGamma || gamma < 0) return hipErrorInvalidValue;
+  const int G = 64 / B;
+  const int nparts = kColParts;
+  const int waves = nparts / G;
+  const int rows = (g.n + nparts - 1) / nparts;
+  // scratch layout (see kColScratchBytes)
+  char* base = static_cast<char*>(scratch);
+  const size_t cells = static_cast<size_t>(nparts) * 64;
+  T* pv = reinterpret_cast<T*>(base);
+  int* pi = reinterpret_cast<int*>(base + cells * kMaxGamma * sizeof(double));
+  T* pmx = reinterpret_cast<T*>(base + cells * kMaxGamma * (sizeof(double) + sizeof(int)));
+  T* pmn = pmx + cells;
+  int* act = reinterpret_cast<int*>(pmn + cells);             // [64][kColParts]
+  int* nact = act + cells;                                     // [64]
+  T* thr = reinterpret_cast<T*>(nact + 64);                    // [64]
+  SC_DISPATCH_B(B, (k_colmax<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(g.n, rows, Y,
+                                                                                pmx, pmn)));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64, 0, st>>>(gamma, nparts, pmx, pmn, thr, nact,
                                                               cs)));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (gamma > 0) {
+    SC_DISPATCH_B(B, (k_colscan<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(
+                          g.n, rows, gamma, Y, pmx, thr, pv, pi, nact, act)));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  SC_DISPATCH_B(B, (k_colmerge<T, kB><<<ncols, 64, 0, st>>>(g.n, s0, gamma, g.rowptr, g.col, Y,
+                                                             pv, pi, nact, act, cs)));
   return hipGetLastError();
 }
 
@@ -341,9 +528,9 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
 }
 
 template hipError_t launch_colstats<float>(const DeviceGraph&, int, int, int, const float*,
-                                           ColStats*, hipStream_t);
+                                           ColStats*, void*, hipStream_t);
 template hipError_t launch_colstats<double>(const DeviceGraph&, int, int, int, const double*,
-                                            ColStats*, hipStream_t);
+                                            ColStats*, void*, hipStream_t);
 template hipError_t launch_walk_counts<float>(const DeviceGraph&, int, int, int, int, int, int,
                                               double, int64_t, const float*, const ColStats*,
                                               const int32_t*, int64_t*, unsigned long long*,

@@ -67,8 +67,10 @@ __global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* 
 
 // ------------------------------------------------------------------ indicator masks
 // One wave per source column; lanes stride over N(s).
+// anymask holds one bit per node: set when any column of the block marks it.
 __global__ void k_mask_set(int n, int s0, int B, const int32_t* __restrict__ rowptr,
-                           const int32_t* __restrict__ col, unsigned long long* mask, int clear) {
+                           const int32_t* __restrict__ col, unsigned long long* mask,
+                           unsigned* anymask, int clear) {
   const int c = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int s = s0 + c;
@@ -76,10 +78,14 @@ __global__ void k_mask_set(int n, int s0, int B, const int32_t* __restrict__ row
   const unsigned long long bit = 1ull << c;
   for (int k = rowptr[s] + lane; k < rowptr[s + 1]; k += 64) {
     const int u = col[k];
-    if (clear)
+    if (clear) {
+      // every bit still set belongs to this block, so whole words can be cleared
       mask[u] = 0ull;
-    else
+      anymask[u >> 5] = 0u;
+    } else {
       atomicOr(&mask[u], bit);
+      atomicOr(&anymask[u >> 5], 1u << (u & 31));
+    }
   }
 }
 
@@ -92,12 +98,25 @@ __device__ inline T reduce_groups(T v) {
   return v;
 }
 
+// wave-uniform broadcast of lane jj's value through a scalar register
+__device__ inline float bcast(float v, int jj) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), jj));
+}
+__device__ inline double bcast(double v, int jj) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFll), jj);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), jj);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
 // ------------------------------------------------------------------ Y2 from masks
 template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void k_twohop(const Task* __restrict__ tasks, int ntasks,
                                                      const int32_t* __restrict__ col,
                                                      const T* __restrict__ inv_deg,
                                                      const unsigned long long* __restrict__ mask,
+                                                     const unsigned* __restrict__ anymask,
                                                      T* __restrict__ Y, T* __restrict__ partials) {
   constexpr int G = 64 / B;
   const int lane = threadIdx.x & 63;
@@ -110,15 +129,31 @@ __global__ __launch_bounds__(kThreads) void k_twohop(const Task* __restrict__ ta
   for (int base = tk.beg; base < tk.end; base += 64) {
     const int cnt = min(64, tk.end - base);
     const int myu = lane < cnt ? col[base + lane] : 0;
-    const unsigned long long mym = lane < cnt ? mask[myu] : 0ull;
-    const T myw = lane < cnt ? inv_deg[myu] : T(0);
-    // uniform trip count: every lane takes part in each shuffle (a shuffle
-    // from an inactive lane would read 0), the add is predicated instead
-    for (int j0 = 0; j0 < cnt; j0 += G) {
-      const int jj = j0 + gq;
-      const unsigned long long mk = __shfl(mym, jj, 64);
-      const T w = __shfl(myw, jj, 64);
-      if (jj < cnt && ((mk >> c) & 1ull)) acc += w;
+    // the small bitmap filters out the neighbours no column marks
+    const bool hit = lane < cnt && ((anymask[myu >> 5] >> (myu & 31)) & 1u);
+    const unsigned long long mym = hit ? mask[myu] : 0ull;
+    const T myw = hit ? inv_deg[myu] : T(0);
+    if (__ballot(hit) == 0ull) continue;
+    if (G == 1) {
+      // one row per wave: broadcast each neighbour's mask and weight through
+      // scalar registers
+      const int mlo = static_cast<int>(mym & 0xFFFFFFFFull);
+      const int mhi = static_cast<int>(mym >> 32);
+      for (int jj = 0; jj < cnt; ++jj) {
+        const unsigned long long mk =
+            (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readlane(mhi, jj))) << 32) |
+            static_cast<unsigned>(__builtin_amdgcn_readlane(mlo, jj));
+        if ((mk >> c) & 1ull) acc += bcast(myw, jj);
+      }
+    } else {
+      // uniform trip count: every lane takes part in each shuffle (a shuffle
+      // from an inactive lane would read 0), the add is predicated instead
+      for (int j0 = 0; j0 < cnt; j0 += G) {
+        const int jj = j0 + gq;
+        const unsigned long long mk = __shfl(mym, jj, 64);
+        const T w = __shfl(myw, jj, 64);
+        if (jj < cnt && ((mk >> c) & 1ull)) acc += w;
+      }
     }
   }
   acc = reduce_groups<T, B>(acc);
@@ -298,9 +333,9 @@ hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, i
 }
 
 hipError_t launch_mask_set(const DeviceGraph& g, int s0, int B, unsigned long long* mask,
-                           bool clear, hipStream_t st) {
+                           unsigned* anymask, bool clear, hipStream_t st) {
   k_mask_set<<<grid_for(B, kWavesPerBlock), kThreads, 0, st>>>(g.n, s0, B, g.rowptr, g.col, mask,
-                                                               clear ? 1 : 0);
+                                                               anymask, clear ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -320,10 +355,10 @@ template <>
 const double* inv_deg_of<double>(const DeviceGraph& g) { return g.inv_deg_d; }
 
 template <typename T>
-hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask, T* Y,
-                         T* partials, hipStream_t st) {
+hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
+                         const unsigned* anymask, T* Y, T* partials, hipStream_t st) {
   SC_DISPATCH_B(B, (k_twohop<T, kB><<<grid_for(g.ntasks, kWavesPerBlock), kThreads, 0, st>>>(
-                        g.tasks, g.ntasks, g.col, inv_deg_of<T>(g), mask, Y, partials)));
+                        g.tasks, g.ntasks, g.col, inv_deg_of<T>(g), mask, anymask, Y, partials)));
   return hipGetLastError();
 }
 
@@ -387,9 +422,9 @@ hipError_t launch_multi_axpy(const double* V, int ncols, int64_t ld, const doubl
 }
 
 template hipError_t launch_twohop<float>(const DeviceGraph&, int, const unsigned long long*,
-                                         float*, float*, hipStream_t);
+                                         const unsigned*, float*, float*, hipStream_t);
 template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigned long long*,
-                                          double*, double*, hipStream_t);
+                                          const unsigned*, double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,
                                             float*, hipStream_t);
 template hipError_t launch_propagate<double>(const DeviceGraph&, int, const double*, double*,

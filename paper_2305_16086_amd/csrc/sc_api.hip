@@ -4,7 +4,6 @@
 // Every piece of arithmetic of the method runs in the kernels of
 // kernels_tgt.hip / kernels_plus.hip; this file only builds the CSR, sizes
 // buffers, chooses launch parameters and sequences the launches.
-#include "sc_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -16,95 +15,66 @@
 #include <string>
 #include <vector>
 
-namespace {
+#include "sc_host.hpp"
 
+namespace sc {
+
+namespace {
 thread_local std::string g_last_error = "no error";
+}  // namespace
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess) {                                                        \
-      return fail(e_ == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,                 \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));              \
-    }                                                                              \
-  } while (0)
+}  // namespace sc
 
-template <typename P>
-hipError_t dev_alloc(P** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(P));
+using sc::dev_alloc;
+using sc::dev_free;
+using sc::fail;
+
+void sc_graph::release() {
+  dev_free(d.rowptr);
+  dev_free(d.col);
+  dev_free(d.deg);
+  dev_free(d.slot_row);
+  dev_free(d.slot_half);
+  dev_free(d.half_slot);
+  dev_free(d.inv_deg_f);
+  dev_free(d.inv_deg_d);
+  dev_free(d.tasks);
+  dev_free(d.heavy);
+  if (Y[0]) (void)hipFree(Y[0]);
+  if (Y[1]) (void)hipFree(Y[1]);
+  Y[0] = Y[1] = nullptr;
+  if (partials) (void)hipFree(partials);
+  partials = nullptr;
+  dev_free(mask);
+  dev_free(anymask);
+  dev_free(gacc);
+  dev_free(tau_slot);
+  dev_free(tau_row);
+  dev_free(nr_slot);
+  dev_free(cs);
+  if (colscratch) (void)hipFree(colscratch);
+  colscratch = nullptr;
+  dev_free(work);
+  dev_free(out_dev);
+  dev_free(tau_out_dev);
+  dev_free(nr_out_dev);
+  if (rdiag) (void)hipFree(rdiag);
+  if (roff) (void)hipFree(roff);
+  rdiag = roff = nullptr;
+  rbytes = 0;
+  dev_free(feat);
+  dev_free(zpred);
+  dev_free(cl_s0);
+  dev_free(fb);
+  dev_free(block_flag);
+  for (auto& e : events) (void)hipEventDestroy(e);
+  events.clear();
 }
-
-template <typename P>
-void dev_free(P*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
-}  // namespace
-
-struct sc_graph {
-  sc::DeviceGraph d;
-  int device = 0;
-  std::vector<int32_t> rowptr_h;
-  std::vector<int32_t> deg_h;
-  double lambda_star = -1.0;
-
-  // work buffers, grown on demand
-  void* Y[2] = {nullptr, nullptr};
-  size_t ybytes = 0;
-  void* partials = nullptr;
-  size_t pbytes = 0;
-  unsigned long long* mask = nullptr;
-  double* gacc = nullptr;
-  int32_t* tau_slot = nullptr;
-  int32_t* tau_row = nullptr;
-  int64_t* nr_slot = nullptr;
-  sc::ColStats* cs = nullptr;
-  unsigned long long* work = nullptr;
-  double* out_dev = nullptr;
-  int32_t* tau_out_dev = nullptr;
-  int32_t* tilde_out_dev = nullptr;
-  int64_t* nr_out_dev = nullptr;
-  std::vector<hipEvent_t> events;
-
-  void release() {
-    dev_free(d.rowptr);
-    dev_free(d.col);
-    dev_free(d.deg);
-    dev_free(d.slot_row);
-    dev_free(d.slot_half);
-    dev_free(d.half_slot);
-    dev_free(d.inv_deg_f);
-    dev_free(d.inv_deg_d);
-    dev_free(d.tasks);
-    dev_free(d.heavy);
-    if (Y[0]) (void)hipFree(Y[0]);
-    if (Y[1]) (void)hipFree(Y[1]);
-    Y[0] = Y[1] = nullptr;
-    if (partials) (void)hipFree(partials);
-    partials = nullptr;
-    dev_free(mask);
-    dev_free(gacc);
-    dev_free(tau_slot);
-    dev_free(tau_row);
-    dev_free(nr_slot);
-    dev_free(cs);
-    dev_free(work);
-    dev_free(out_dev);
-    dev_free(tau_out_dev);
-    dev_free(tilde_out_dev);
-    dev_free(nr_out_dev);
-    for (auto& e : events) (void)hipEventDestroy(e);
-    events.clear();
-  }
-};
 
 // ====================================================================== graph build
 
@@ -369,7 +339,10 @@ double ritz_bound(const std::vector<double>& alpha, const std::vector<double>& b
   return std::max(std::fabs(tmax) + rmax, std::fabs(tmin) + rmin);
 }
 
-int compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
+}  // namespace
+
+int sc::compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
+  using namespace sc;
   const int64_t n = g->d.n;
   const int kmax = static_cast<int>(std::min<int64_t>(n - 1, 160));
   const int64_t ld = n;
@@ -458,20 +431,20 @@ int compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
   return SC_OK;
 }
 
-}  // namespace
+int sc::graph_lambda_star(sc_graph* g, hipStream_t st, double* lam) {
+  if (g->lambda_star <= 0.0) {
+    double v = 0.0;
+    const int rc = compute_lambda_star(g, st, &v);
+    if (rc != SC_OK) return rc;
+    g->lambda_star = v;
+  }
+  *lam = g->lambda_star;
+  return SC_OK;
+}
 
 extern "C" int sc_lambda_star(sc_graph* g, double* lam) {
   if (!g || !lam) return fail(SC_EINVAL, "NULL argument");
-  if (g->lambda_star > 0) {
-    *lam = g->lambda_star;
-    return SC_OK;
-  }
-  double v = 0.0;
-  const int rc = compute_lambda_star(g, nullptr, &v);
-  if (rc != SC_OK) return rc;
-  g->lambda_star = v;
-  *lam = v;
-  return SC_OK;
+  return sc::graph_lambda_star(g, nullptr, lam);
 }
 
 // ====================================================================== all-edge SC
@@ -488,11 +461,15 @@ extern "C" void sc_default_options(sc_options* o) {
   o->tilde_tau = -1;
   o->max_L = 255;
   o->lambda_star = 0.0;
+  o->mlp = nullptr;
+  o->infer_bf16 = 1;
+  o->force_fallback = 0;
 }
 
-namespace {
+namespace sc {
 
 int ensure_buffers(sc_graph* g, int B, size_t tsize) {
+  using namespace sc;
   const int64_t n = g->d.n;
   const int64_t S = static_cast<int64_t>(g->rowptr_h[n]);
   const size_t yb = static_cast<size_t>(n) * B * tsize;
@@ -517,16 +494,25 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->mask) {
     HIP_TRY(dev_alloc(&g->mask, n));
     HIP_TRY(hipMemset(g->mask, 0, n * sizeof(unsigned long long)));
+    HIP_TRY(dev_alloc(&g->anymask, (n + 31) / 32));
+    HIP_TRY(hipMemset(g->anymask, 0, (n + 31) / 32 * sizeof(unsigned)));
   }
   if (!g->gacc) HIP_TRY(dev_alloc(&g->gacc, S));
   if (!g->tau_slot) HIP_TRY(dev_alloc(&g->tau_slot, S));
   if (!g->tau_row) HIP_TRY(dev_alloc(&g->tau_row, n));
   if (!g->nr_slot) HIP_TRY(dev_alloc(&g->nr_slot, S));
   if (!g->cs) HIP_TRY(dev_alloc(&g->cs, 64));
+  if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
   if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
   return SC_OK;
 }
+
+}  // namespace sc
+
+namespace {
+
+using sc::Runner;
 
 struct CostModel {
   double gather_bw;   // bytes/s for the neighbour gathers of one dense step
@@ -543,117 +529,6 @@ CostModel cost_model() {
 }
 
 template <typename T>
-struct Runner {
-  sc_graph* g;
-  int B;
-  hipStream_t st;
-  bool timing;
-  sc_stats stats{};
-  size_t ev_used = 0;
-  int cur = 0;   // index of Y holding the current step
-
-  T* Yb(int i) { return static_cast<T*>(g->Y[i]); }
-  T* parts() { return static_cast<T*>(g->partials); }
-
-  int event_pair(hipEvent_t* a, hipEvent_t* b) {
-    while (g->events.size() < ev_used + 2) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      g->events.push_back(e);
-    }
-    *a = g->events[ev_used];
-    *b = g->events[ev_used + 1];
-    ev_used += 2;
-    return SC_OK;
-  }
-
-  double step_bytes() const {
-    const double n = g->d.n, S = static_cast<double>(g->rowptr_h[g->d.n]);
-    return 2.0 * n * B * sizeof(T) + 4.0 * S + 16.0 * g->d.ntasks + sizeof(T) * n;
-  }
-
-  // traverse block [s0, s0+B) from l = 2 up to l = lend, accumulating when acc
-  int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc) {
-    if (lend < 2) return SC_OK;
-    HIP_TRY(sc::launch_mask_set(g->d, s0, B, g->mask, false, st));
-    cur = 0;
-    HIP_TRY(sc::launch_twohop<T>(g->d, B, g->mask, Yb(cur), parts(), st));
-    HIP_TRY(sc::launch_fixup<T>(g->d, B, parts(), Yb(cur), st));
-    HIP_TRY(sc::launch_mask_set(g->d, s0, B, g->mask, true, st));
-    if (acc) HIP_TRY(sc::launch_accumulate<T>(g->d, kbeg, kend, s0, B, 2, Yb(cur), g->tau_slot, gacc, st));
-    for (int ell = 3; ell <= lend; ++ell) {
-      hipEvent_t a = nullptr, b = nullptr;
-      if (timing) {
-        int rc = event_pair(&a, &b);
-        if (rc) return rc;
-        HIP_TRY(hipEventRecord(a, st));
-      }
-      HIP_TRY(sc::launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), st));
-      if (timing) HIP_TRY(hipEventRecord(b, st));
-      ++stats.prop_launches;
-      stats.prop_bytes += step_bytes();
-      HIP_TRY(sc::launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
-      cur = 1 - cur;
-      if (acc) HIP_TRY(sc::launch_accumulate<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), g->tau_slot, gacc, st));
-    }
-    return SC_OK;
-  }
-
-  // Y for l in {0, 1} when the walk tail starts that early
-  int init_low(int s0, int ell) {
-    HIP_TRY(hipMemsetAsync(Yb(0), 0, g->ybytes, st));
-    cur = 0;
-    // p_0 = e_s; p_1(x, s) = 1/d_x for x in N(s): one-hop scatter via the mask kernel's pattern
-    return ell <= 1 ? init_indicator(s0, ell) : SC_OK;
-  }
-  int init_indicator(int s0, int ell);
-};
-
-__global__ void k_init_low_float(int n, int s0, int B, int ell, const int32_t* rowptr,
-                                 const int32_t* col, const float* inv_deg, float* Y) {
-  const int c = blockIdx.x;
-  const int s = s0 + c;
-  if (s >= n) return;
-  if (ell == 0) {
-    if (threadIdx.x == 0) Y[static_cast<size_t>(s) * B + c] = 1.0f;
-    return;
-  }
-  for (int k = rowptr[s] + threadIdx.x; k < rowptr[s + 1]; k += blockDim.x) {
-    const int x = col[k];
-    Y[static_cast<size_t>(x) * B + c] = inv_deg[x];
-  }
-}
-__global__ void k_init_low_double(int n, int s0, int B, int ell, const int32_t* rowptr,
-                                  const int32_t* col, const double* inv_deg, double* Y) {
-  const int c = blockIdx.x;
-  const int s = s0 + c;
-  if (s >= n) return;
-  if (ell == 0) {
-    if (threadIdx.x == 0) Y[static_cast<size_t>(s) * B + c] = 1.0;
-    return;
-  }
-  for (int k = rowptr[s] + threadIdx.x; k < rowptr[s + 1]; k += blockDim.x) {
-    const int x = col[k];
-    Y[static_cast<size_t>(x) * B + c] = inv_deg[x];
-  }
-}
-
-template <>
-int Runner<float>::init_indicator(int s0, int ell) {
-  k_init_low_float<<<B, 64, 0, st>>>(g->d.n, s0, B, ell, g->d.rowptr, g->d.col, g->d.inv_deg_f,
-                                     Yb(0));
-  HIP_TRY(hipGetLastError());
-  return SC_OK;
-}
-template <>
-int Runner<double>::init_indicator(int s0, int ell) {
-  k_init_low_double<<<B, 64, 0, st>>>(g->d.n, s0, B, ell, g->d.rowptr, g->d.col, g->d.inv_deg_d,
-                                      Yb(0));
-  HIP_TRY(hipGetLastError());
-  return SC_OK;
-}
-
-template <typename T>
 int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_user,
                sc_stats* st_user) {
   const int64_t n = g->d.n, m = g->d.m;
@@ -665,7 +540,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   if (gamma > sc::kMaxGamma) return fail(SC_EINVAL, "gamma above 16 is not supported");
   int max_L = o.max_L > 0 ? o.max_L : 255;
   if (max_L % 2 == 0) --max_L;
-  int rc = ensure_buffers(g, B, sizeof(T));
+  int rc = sc::ensure_buffers(g, B, sizeof(T));
   if (rc) return rc;
   const bool dev_ptrs = (o.flags & SC_DEVICE_PTRS) != 0;
 
@@ -686,13 +561,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     if (o.lambda_star > 0.0) {
       lam = o.lambda_star;
     } else {
-      if (g->lambda_star <= 0.0) {
-        double v = 0.0;
-        rc = compute_lambda_star(g, st, &v);
-        if (rc) return rc;
-        g->lambda_star = v;
-      }
-      lam = g->lambda_star;
+      rc = sc::graph_lambda_star(g, st, &lam);
+      if (rc) return rc;
     }
     if (!(lam > 0.0 && lam < 1.0)) return fail(SC_EINVAL, "lambda* must lie in (0, 1)");
   }
@@ -712,13 +582,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
 
   const int nblocks = static_cast<int>((n + B - 1) / B);
   auto block_range = [&](int b, int* s0, int* kbeg, int* kend, int* tmax) {
-    *s0 = b * B;
-    const int s1 = static_cast<int>(std::min<int64_t>(n, *s0 + B));
-    *kbeg = g->rowptr_h[*s0];
-    *kend = g->rowptr_h[s1];
-    int t = 0;
-    for (int x = *s0; x < s1; ++x) t = std::max(t, tau_row[x]);
-    *tmax = t;
+    R.block_range(b, tau_row, s0, kbeg, kend, tmax);
   };
 
   int tilde = Lmax;
@@ -748,7 +612,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
             rc = R.traverse(s0, kbeg, kend, ell, false, nullptr);
             if (rc) return rc;
             HIP_TRY(hipMemsetAsync(g->work, 0, 2 * sizeof(unsigned long long), st));
-            HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, st));
+            HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, st));
             HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, ell, gamma, coef, nr_cap,
                                               R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot,
                                               g->work, st));
@@ -785,7 +649,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
         rc = R.init_low(s0, tilde);
         if (rc) return rc;
       }
-      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, st));
+      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, st));
       HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
                                         R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, work, st));
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
@@ -861,14 +725,18 @@ extern "C" int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options*
     opt = *o;
   else
     sc_default_options(&opt);
-  if (opt.method != SC_TGT && opt.method != SC_TGT_PLUS)
+  if (opt.method != SC_TGT && opt.method != SC_TGT_PLUS && opt.method != SC_LEARNED)
     return fail(SC_EINVAL, "unknown method");
   if (opt.precision != 0 && opt.precision != 1) return fail(SC_EINVAL, "precision must be 0 or 1");
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != g->device) (void)hipSetDevice(g->device);
-  const int rc = opt.precision == 1 ? run_method<double>(g, eps, L, opt, out, st)
-                                    : run_method<float>(g, eps, L, opt, out, st);
+  int rc;
+  if (opt.method == SC_LEARNED)
+    rc = sc::run_learned(g, eps, opt, out, st);
+  else
+    rc = opt.precision == 1 ? run_method<double>(g, eps, L, opt, out, st)
+                            : run_method<float>(g, eps, L, opt, out, st);
   if (cur != g->device) (void)hipSetDevice(cur);
   return rc;
 }
@@ -895,6 +763,6 @@ extern "C" const char* sc_strerror(int code) {
   }
 }
 
-extern "C" const char* sc_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* sc_last_error(void) { return sc::g_last_error.c_str(); }
 
 extern "C" const char* sc_version(void) { return "sc-mi355x 0.1 (gfx950)"; }

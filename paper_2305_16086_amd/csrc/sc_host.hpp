@@ -1,0 +1,208 @@
+// Host-side pieces shared by the translation units of libsc: error reporting,
+// the graph handle, work buffers and the per-block traversal driver.
+#pragma once
+
+#include "sc_internal.hpp"
+
+#include <string>
+#include <vector>
+
+namespace sc {
+
+// Records the message for sc_last_error() and returns code.
+int fail(int code, const std::string& msg);
+
+template <typename P>
+hipError_t dev_alloc(P** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(P));
+}
+
+template <typename P>
+void dev_free(P*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace sc
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      return ::sc::fail(e_ == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,           \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    }                                                                              \
+  } while (0)
+
+struct sc_graph {
+  sc::DeviceGraph d;
+  int device = 0;
+  std::vector<int32_t> rowptr_h;
+  std::vector<int32_t> deg_h;
+  double lambda_star = -1.0;
+
+  // work buffers, grown on demand
+  void* Y[2] = {nullptr, nullptr};
+  size_t ybytes = 0;
+  void* partials = nullptr;
+  size_t pbytes = 0;
+  unsigned long long* mask = nullptr;
+  unsigned* anymask = nullptr;   // one bit per node
+  double* gacc = nullptr;
+  int32_t* tau_slot = nullptr;
+  int32_t* tau_row = nullptr;
+  int64_t* nr_slot = nullptr;
+  sc::ColStats* cs = nullptr;
+  void* colscratch = nullptr;  // sc::kColScratchBytes
+  unsigned long long* work = nullptr;
+  double* out_dev = nullptr;
+  int32_t* tau_out_dev = nullptr;
+  int64_t* nr_out_dev = nullptr;
+  // learned closure buffers
+  void* rdiag = nullptr;
+  void* roff = nullptr;
+  size_t rbytes = 0;
+  float* feat = nullptr;       // [m][16]
+  float* zpred = nullptr;      // [m]
+  double* cl_s0 = nullptr;     // [m] x 4: s0, uK, lo, hi
+  unsigned char* fb = nullptr; // [m]
+  int* block_flag = nullptr;   // [nblocks of width 16]
+  std::vector<hipEvent_t> events;
+
+  void release();
+};
+
+namespace sc {
+
+int ensure_buffers(sc_graph* g, int B, size_t tsize);
+int ensure_closure_buffers(sc_graph* g, size_t tsize);
+int compute_lambda_star(sc_graph* g, hipStream_t st, double* out);
+int graph_lambda_star(sc_graph* g, hipStream_t st, double* out);
+
+template <typename T>
+__global__ void k_init_low(int n, int s0, int B, int ell, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ col, const T* __restrict__ inv_deg,
+                           T* __restrict__ Y) {
+  const int c = blockIdx.x;
+  const int s = s0 + c;
+  if (s >= n) return;
+  if (ell == 0) {
+    if (threadIdx.x == 0) Y[static_cast<size_t>(s) * B + c] = T(1);
+    return;
+  }
+  for (int k = rowptr[s] + threadIdx.x; k < rowptr[s + 1]; k += blockDim.x) {
+    const int x = col[k];
+    Y[static_cast<size_t>(x) * B + c] = inv_deg[x];   // p_1(x, s) = 1/d_x for x in N(s)
+  }
+}
+
+template <typename T>
+inline const T* inv_deg_host_sel(const DeviceGraph& g);
+template <>
+inline const float* inv_deg_host_sel<float>(const DeviceGraph& g) { return g.inv_deg_f; }
+template <>
+inline const double* inv_deg_host_sel<double>(const DeviceGraph& g) { return g.inv_deg_d; }
+
+// Drives the launches of one source block [s0, s0+B).
+template <typename T>
+struct Runner {
+  sc_graph* g;
+  int B;
+  hipStream_t st;
+  bool timing;
+  sc_stats stats{};
+  size_t ev_used = 0;
+  int cur = 0;            // index of the Y buffer holding the latest step
+  T* rdiag = nullptr;     // optional per-slot recordings of p_l(s,s), p_l(j,s)
+  T* roff = nullptr;
+  int record_to = -1;     // record steps 2..record_to
+
+  T* Yb(int i) { return static_cast<T*>(g->Y[i]); }
+  T* parts() { return static_cast<T*>(g->partials); }
+
+  int event_pair(hipEvent_t* a, hipEvent_t* b) {
+    while (g->events.size() < ev_used + 2) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      g->events.push_back(e);
+    }
+    *a = g->events[ev_used];
+    *b = g->events[ev_used + 1];
+    ev_used += 2;
+    return SC_OK;
+  }
+
+  // algorithmic bytes of one dense propagation launch: the state read once and
+  // written once, the CSR column array, the task list and the degree vector
+  double step_bytes() const {
+    const double n = g->d.n, S = static_cast<double>(g->rowptr_h[g->d.n]);
+    return 2.0 * n * B * sizeof(T) + 4.0 * S + 16.0 * g->d.ntasks + sizeof(T) * n;
+  }
+
+  int after_step(int s0, int kbeg, int kend, int ell, bool acc, double* gacc) {
+    if (acc)
+      HIP_TRY(launch_accumulate<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), g->tau_slot, gacc, st));
+    if (rdiag && ell <= record_to)
+      HIP_TRY(launch_record<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), rdiag, roff, st));
+    return SC_OK;
+  }
+
+  // traverse the block from l = 2 up to l = lend (l = 0, 1 are closed form)
+  int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc) {
+    if (lend < 2) return SC_OK;
+    HIP_TRY(launch_mask_set(g->d, s0, B, g->mask, g->anymask, false, st));
+    cur = 0;
+    HIP_TRY(launch_twohop<T>(g->d, B, g->mask, g->anymask, Yb(cur), parts(), st));
+    HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(cur), st));
+    HIP_TRY(launch_mask_set(g->d, s0, B, g->mask, g->anymask, true, st));
+    int rc = after_step(s0, kbeg, kend, 2, acc, gacc);
+    if (rc) return rc;
+    for (int ell = 3; ell <= lend; ++ell) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (timing) {
+        rc = event_pair(&a, &b);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(a, st));
+      }
+      HIP_TRY(launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), st));
+      if (timing) HIP_TRY(hipEventRecord(b, st));
+      ++stats.prop_launches;
+      stats.prop_bytes += step_bytes();
+      HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
+      cur = 1 - cur;
+      rc = after_step(s0, kbeg, kend, ell, acc, gacc);
+      if (rc) return rc;
+    }
+    return SC_OK;
+  }
+
+  // state at l = 0 (indicators) or l = 1 (one hop) when the walk tail starts that early
+  int init_low(int s0, int ell) {
+    HIP_TRY(hipMemsetAsync(Yb(0), 0, g->ybytes, st));
+    cur = 0;
+    k_init_low<T><<<B, 64, 0, st>>>(g->d.n, s0, B, ell, g->d.rowptr, g->d.col,
+                                    inv_deg_host_sel<T>(g->d), Yb(0));
+    HIP_TRY(hipGetLastError());
+    return SC_OK;
+  }
+
+  // a block's source range, slot range and largest truncation
+  void block_range(int b, const std::vector<int32_t>& tau_row, int* s0, int* kbeg, int* kend,
+                   int* tmax) const {
+    const int64_t n = g->d.n;
+    *s0 = b * B;
+    const int s1 = static_cast<int>(std::min<int64_t>(n, static_cast<int64_t>(*s0) + B));
+    *kbeg = g->rowptr_h[*s0];
+    *kend = g->rowptr_h[s1];
+    int t = 0;
+    for (int x = *s0; x < s1; ++x) t = std::max(t, tau_row[x]);
+    *tmax = t;
+  }
+};
+
+// learned closure run (method SC_LEARNED)
+int run_learned(sc_graph* g, double eps, const sc_options& o, double* out_user, sc_stats* st);
+
+}  // namespace sc

@@ -76,12 +76,12 @@ hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, i
 
 // Source block [s0, s0+B): mark bit c of mask[u] for every u in N(s0+c).
 hipError_t launch_mask_set(const DeviceGraph& g, int s0, int B, unsigned long long* mask,
-                           bool clear, hipStream_t st);
+                           unsigned* anymask, bool clear, hipStream_t st);
 
 // Y2 = P P Y0 for the indicator block via the neighbour masks.
 template <typename T>
-hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask, T* Y,
-                         T* partials, hipStream_t st);
+hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
+                         const unsigned* anymask, T* Y, T* partials, hipStream_t st);
 
 // Yn = P Yp (dense block gather), chunked rows write partial sums.
 template <typename T>
@@ -98,9 +98,15 @@ hipError_t launch_accumulate(const DeviceGraph& g, int kbeg, int kend, int s0, i
                              const T* Y, const int32_t* tau_slot, double* gacc, hipStream_t st);
 
 // Algorithm 3 summary per column of the block (top-gamma, rho bound, extremes).
+// scratch: kColScratchBytes of device memory.
+constexpr int kColParts = 2048;  // row chunks of the coalesced first pass (multiple of 4 * 64/B)
+constexpr size_t kColScratchBytes =
+    static_cast<size_t>(kColParts) * 64 *
+        (kMaxGamma * (sizeof(double) + sizeof(int)) + 2 * sizeof(double) + sizeof(int)) +
+    64 * (sizeof(int) + sizeof(double));
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
-                           ColStats* cs, hipStream_t st);
+                           ColStats* cs, void* scratch, hipStream_t st);
 
 // n_r per slot (Eq. 13 with chi of Eq. 17 / Eq. 15); 0 where tau_k <= tilde.
 template <typename T>
@@ -124,6 +130,41 @@ hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,
 // Trace outputs in input order.
 hipError_t launch_trace(const DeviceGraph& g, const int32_t* tau_slot, const int64_t* nr_slot,
                         int32_t* tau_out, int64_t* nr_out, hipStream_t st);
+
+// --------------------------------------------------------------- learned closure
+constexpr int kMlpParams = 5313;
+constexpr int kFeat = 16;
+constexpr int kRecSteps = 8;   // L0
+
+template <typename T>
+hipError_t launch_record_init(const DeviceGraph& g, T* rdiag, T* roff, hipStream_t st);
+template <typename T>
+hipError_t launch_record(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
+                         const T* Y, T* rdiag, T* roff, hipStream_t st);
+template <typename T>
+hipError_t launch_features(const DeviceGraph& g, const T* rdiag, const T* roff, double lam,
+                           float* X, double* s0, double* uK, double* lo, double* hi,
+                           hipStream_t st);
+hipError_t launch_targets(int64_t m, const double* s_ref, const double* s0, const double* uK,
+                          float* z, float* w, hipStream_t st);
+hipError_t launch_norm_stats(const float* X, int64_t N, float* norm, hipStream_t st);
+hipError_t launch_feature_range(const float* X, int64_t N, float* fmin, float* fmax,
+                                hipStream_t st);
+hipError_t launch_mlp_train_step(const float* theta, const float* norm, const float* X,
+                                 const float* z, const float* w, const int64_t* idx,
+                                 int64_t nbatch, float inv_count, float* grads, float* lossp,
+                                 float* grad, float* loss_out, hipStream_t st);
+hipError_t launch_adam(float* theta, const float* grad, float* m1, float* m2, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t st);
+hipError_t launch_mlp_infer(const float* theta, const float* norm, const float* X, int64_t N,
+                            int bf16, float* y, hipStream_t st);
+hipError_t launch_closure_apply(const DeviceGraph& g, const float* zpred, const double* s0,
+                                const double* uK, const double* lo, const double* hi,
+                                const float* X, const float* fmin, const float* fmax, double eps,
+                                int B, int force, double* out, unsigned char* fb,
+                                int* block_flag, unsigned long long* count, hipStream_t st);
+hipError_t launch_combine_masked(const DeviceGraph& g, const double* gacc,
+                                 const unsigned char* fb, double* out, hipStream_t st);
 
 // --------------------------------------------------------------- Lanczos helpers
 hipError_t launch_nmat_spmv(const DeviceGraph& g, const double* sid, const double* x,

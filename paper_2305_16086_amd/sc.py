@@ -31,6 +31,8 @@ SC_TIME_KERNELS = 0x4
 
 SC_TGT = 0
 SC_TGT_PLUS = 1
+SC_LEARNED = 2
+MLP_PARAMS = 5313
 
 
 class ScOptions(C.Structure):
@@ -49,6 +51,19 @@ class ScOptions(C.Structure):
         ("tau_out", C.c_void_p),
         ("tilde_tau_out", C.c_void_p),
         ("nr_out", C.c_void_p),
+        ("mlp", C.c_void_p),
+        ("infer_bf16", C.c_int),
+        ("force_fallback", C.c_int),
+    ]
+
+
+class ScTrainOptions(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int),
+        ("batch", C.c_int),
+        ("lr", C.c_float),
+        ("seed", C.c_uint64),
+        ("stream", C.c_void_p),
     ]
 
 
@@ -65,6 +80,7 @@ class ScStats(C.Structure):
         ("prop_ms", C.c_double),
         ("prop_bytes", C.c_double),
         ("total_ms", C.c_double),
+        ("fallback_edges", C.c_int64),
     ]
 
     def as_dict(self):
@@ -103,6 +119,31 @@ def _load():
     lib.sc_last_error.restype = C.c_char_p
     lib.sc_version.argtypes = []
     lib.sc_version.restype = C.c_char_p
+    lib.sc_default_train_options.argtypes = [C.POINTER(ScTrainOptions)]
+    lib.sc_default_train_options.restype = None
+    lib.sc_mlp_create.argtypes = [C.c_uint64, C.POINTER(C.c_void_p)]
+    lib.sc_mlp_create.restype = C.c_int
+    lib.sc_mlp_free.argtypes = [C.c_void_p]
+    lib.sc_mlp_free.restype = None
+    lib.sc_mlp_get.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.sc_mlp_get.restype = C.c_int
+    lib.sc_mlp_set.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.sc_mlp_set.restype = C.c_int
+    lib.sc_closure_dataset.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+    lib.sc_closure_dataset.restype = C.c_int
+    lib.sc_closure_features.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.sc_closure_features.restype = C.c_int
+    lib.sc_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.POINTER(ScTrainOptions), C.c_void_p]
+    lib.sc_mlp_train.restype = C.c_int
+    lib.sc_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.sc_mlp_grad.restype = C.c_int
+    lib.sc_mlp_predict.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
+                                   C.c_void_p]
+    lib.sc_mlp_predict.restype = C.c_int
     return lib
 
 
@@ -111,7 +152,9 @@ _lib = _load()
 # names declared in include/sc.h, for the export check
 EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_graph",
             "sc_lambda_star", "sc_all_edges", "sc_all_edges_ex", "sc_strerror",
-            "sc_last_error", "sc_version"]
+            "sc_last_error", "sc_version", "sc_default_train_options", "sc_mlp_create",
+            "sc_mlp_free", "sc_mlp_get", "sc_mlp_set", "sc_closure_dataset",
+            "sc_closure_features", "sc_mlp_train", "sc_mlp_grad", "sc_mlp_predict"]
 
 
 def _check(rc, where):
@@ -249,3 +292,138 @@ def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = No
     rc = _lib.sc_all_edges_ex(g.handle, float(eps), int(L), C.byref(o), _ptr(out), C.byref(st))
     _check(rc, "sc_all_edges_ex")
     return out, st.as_dict()
+
+
+# ---------------------------------------------------------------- learned closure
+
+class Mlp:
+    """Owning wrapper of an sc_mlp handle."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("network already freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            _lib.sc_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _stream_of(t):
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _dev(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or t.numel() != numel \
+            or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor with {numel} elements")
+    return t.data_ptr()
+
+
+def sc_default_train_options(**kw) -> ScTrainOptions:
+    t = ScTrainOptions()
+    _lib.sc_default_train_options(C.byref(t))
+    for k, v in kw.items():
+        if not hasattr(t, k):
+            raise KeyError(k)
+        setattr(t, k, v)
+    return t
+
+
+def sc_mlp_create(seed: int = 1) -> Mlp:
+    h = C.c_void_p()
+    _check(_lib.sc_mlp_create(int(seed), C.byref(h)), "sc_mlp_create")
+    return Mlp(h)
+
+
+def sc_mlp_free(net: Mlp):
+    net.free()
+
+
+def sc_mlp_get(net: Mlp):
+    p = np.empty(MLP_PARAMS, np.float32)
+    nrm = np.empty(32, np.float32)
+    rng = np.empty(32, np.float32)
+    _check(_lib.sc_mlp_get(net.handle, p.ctypes.data, nrm.ctypes.data, rng.ctypes.data), "sc_mlp_get")
+    return p, nrm, rng
+
+
+def sc_mlp_set(net: Mlp, params=None, norm=None, range_=None):
+    def arr(x, k):
+        if x is None:
+            return None, None
+        a = np.ascontiguousarray(x, dtype=np.float32)
+        if a.size != k:
+            raise ValueError(f"expected {k} floats")
+        return a, a.ctypes.data
+    pa, pp = arr(params, MLP_PARAMS)
+    na, npp = arr(norm, 32)
+    ra, rp = arr(range_, 32)
+    _check(_lib.sc_mlp_set(net.handle, pp, npp, rp), "sc_mlp_set")
+
+
+def sc_closure_dataset(g: Graph, L_ref: int, precision: int, X, z, w):
+    """X: CUDA float32 [m,16]; z, w: CUDA float32 [m]."""
+    import torch
+    _check(_lib.sc_closure_dataset(g.handle, int(L_ref), int(precision),
+                                   _dev(X, torch.float32, 16 * g.m, "X"),
+                                   _dev(z, torch.float32, g.m, "z"),
+                                   _dev(w, torch.float32, g.m, "w"), _stream_of(X)),
+           "sc_closure_dataset")
+
+
+def sc_closure_features(g: Graph, precision: int, X, s0=None, uK=None, lo=None, hi=None):
+    import torch
+    ptr = lambda t, nm: None if t is None else _dev(t, torch.float64, g.m, nm)  # noqa: E731
+    _check(_lib.sc_closure_features(g.handle, int(precision), _dev(X, torch.float32, 16 * g.m, "X"),
+                                    ptr(s0, "s0"), ptr(uK, "uK"), ptr(lo, "lo"), ptr(hi, "hi"),
+                                    _stream_of(X)), "sc_closure_features")
+
+
+def sc_mlp_train(net: Mlp, X, z, w, options: ScTrainOptions | None = None):
+    import torch
+    N = z.numel()
+    t = options if options is not None else sc_default_train_options()
+    if not t.stream:
+        t.stream = _stream_of(X)
+    losses = np.zeros(max(t.epochs, 1), np.float32)
+    _check(_lib.sc_mlp_train(net.handle, _dev(X, torch.float32, 16 * N, "X"),
+                             _dev(z, torch.float32, N, "z"),
+                             None if w is None else _dev(w, torch.float32, N, "w"), N,
+                             C.byref(t), losses.ctypes.data), "sc_mlp_train")
+    return losses[: t.epochs]
+
+
+def sc_mlp_grad(net: Mlp, X, z, w=None):
+    import torch
+    N = z.numel()
+    g = np.empty(MLP_PARAMS, np.float32)
+    loss = np.empty(1, np.float32)
+    _check(_lib.sc_mlp_grad(net.handle, _dev(X, torch.float32, 16 * N, "X"),
+                            _dev(z, torch.float32, N, "z"),
+                            None if w is None else _dev(w, torch.float32, N, "w"), N,
+                            g.ctypes.data, loss.ctypes.data, _stream_of(X)), "sc_mlp_grad")
+    return g, float(loss[0])
+
+
+def sc_mlp_predict(net: Mlp, X, bf16: int = 1, y=None):
+    import torch
+    N = X.numel() // 16
+    if y is None:
+        y = torch.empty(N, dtype=torch.float32, device=X.device)
+    _check(_lib.sc_mlp_predict(net.handle, _dev(X, torch.float32, 16 * N, "X"), N, int(bf16),
+                               _dev(y, torch.float32, N, "y"), _stream_of(X)), "sc_mlp_predict")
+    return y
