@@ -1,8 +1,13 @@
 // Deterministic traversal kernels (Algorithm 2) for a block of B sources.
 //
 // Layout: the block state Y is node-major, Y[x * B + c] = p_l(x, s0 + c), so
-// gathering a neighbour row reads B contiguous values.  Every reduction has a
-// fixed order (no floating-point atomics), so results are bit-reproducible.
+// gathering a neighbour row reads B contiguous values.  Every floating-point
+// reduction has a fixed order (no floating-point atomics), so results are
+// bit-reproducible.  A row with at most kChunk neighbours is one wave's task;
+// a heavier row is one workgroup's task (its four waves take interleaved
+// 64-slot pieces and add their sums in wave order through LDS); a row above
+// kGiant neighbours is cut into workgroup chunks whose partial sums a fix-up
+// pass adds in chunk order.
 #include "sc_internal.hpp"
 
 #include <cfloat>
@@ -66,25 +71,34 @@ __global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* 
 }
 
 // ------------------------------------------------------------------ indicator masks
-// One wave per source column; lanes stride over N(s).
-// anymask holds one bit per node: set when any column of the block marks it.
-__global__ void k_mask_set(int n, int s0, int B, const int32_t* __restrict__ rowptr,
-                           const int32_t* __restrict__ col, unsigned long long* mask,
-                           unsigned* anymask, int clear) {
-  const int c = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+// Waves [0, B) mark bit c of mask[u] (and the node's bit in anymask) for every
+// u in N(s_set + c) in buffer `buf`; waves [B, 2B) clear what block s_clear
+// marked in the other buffer.  Each buffer only ever holds one block's bits,
+// so clearing may zero whole words.
+__global__ void k_mask_update(int n, int s_set, int s_clear, int B, int buf, int64_t mwords,
+                              int64_t awords, const int32_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, unsigned long long* mask,
+                              unsigned* anymask) {
+  const int w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int s = s0 + c;
-  if (c >= B || s >= n) return;
+  if (w >= 2 * B) return;
+  const bool set = w < B;
+  const int c = set ? w : w - B;
+  const int sb = set ? s_set : s_clear;
+  const int s = sb + c;
+  if (sb < 0 || s >= n) return;
+  const int b = set ? buf : 1 - buf;
+  unsigned long long* mk = mask + static_cast<size_t>(b) * mwords;
+  unsigned* am = anymask + static_cast<size_t>(b) * awords;
   const unsigned long long bit = 1ull << c;
   for (int k = rowptr[s] + lane; k < rowptr[s + 1]; k += 64) {
     const int u = col[k];
-    if (clear) {
-      // every bit still set belongs to this block, so whole words can be cleared
-      mask[u] = 0ull;
-      anymask[u >> 5] = 0u;
+    if (set) {
+      atomicOr(&mk[u], bit);
+      atomicOr(&am[u >> 5], 1u << (u & 31));
     } else {
-      atomicOr(&mask[u], bit);
-      atomicOr(&anymask[u >> 5], 1u << (u & 31));
+      mk[u] = 0ull;
+      am[u >> 5] = 0u;
     }
   }
 }
@@ -110,33 +124,89 @@ __device__ inline double bcast(double v, int jj) {
                               static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
-// ------------------------------------------------------------------ Y2 from masks
+// Pointers the row kernels need (passed by value).
+template <typename T>
+struct RowArgs {
+  const Task* tasks;          // wave tasks (light rows)
+  int ntasks;
+  const Task* wg_tasks;       // workgroup tasks (heavy rows, giant-row chunks)
+  int nwg;
+  int row_blocks;             // nwg + workgroups of wave tasks
+  const int32_t* col;
+  const T* inv_deg;
+  T* partials;
+  // fused accumulation of the previous step (workgroups after row_blocks)
+  const int32_t* slot_row;
+  const double* inv_deg_d;
+  AccJob acc;
+};
+
+// gacc[k] += (Y[s][c] - Y[j][c]) / d_s for slot k = (s -> j), l <= tau_k (Eq. 9)
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_twohop(const Task* __restrict__ tasks, int ntasks,
-                                                     const int32_t* __restrict__ col,
-                                                     const T* __restrict__ inv_deg,
-                                                     const unsigned long long* __restrict__ mask,
-                                                     const unsigned* __restrict__ anymask,
-                                                     T* __restrict__ Y, T* __restrict__ partials) {
+__device__ inline void accumulate_slot(const RowArgs<T>& a, const T* Y, int k) {
+  if (k >= a.acc.kend || a.acc.ell > a.acc.tau[k]) return;
+  const int s = a.slot_row[k];
+  const int c = s - a.acc.s0;
+  const int j = a.col[k];
+  const double pss = static_cast<double>(Y[static_cast<size_t>(s) * B + c]);
+  const double pjs = static_cast<double>(Y[static_cast<size_t>(j) * B + c]);
+  a.acc.gacc[k] += (pss - pjs) * a.inv_deg_d[s];
+}
+
+// Sum over the 64-slot pieces first, first + step, ... of [beg, end) of the
+// neighbour rows of Yp (column c); lanes c, c+B, ... share a column and are
+// combined at the end.
+template <typename T, int B>
+__device__ inline T gather_pieces(const RowArgs<T>& a, const T* __restrict__ Yp, int beg, int end,
+                                  int first, int step, int lane, int c, int gq) {
   constexpr int G = 64 / B;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (t >= ntasks) return;
-  const Task tk = tasks[t];
-  const int c = lane % B;
-  const int gq = lane / B;
+  constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;   // gathers in flight per lane
   T acc = T(0);
-  for (int base = tk.beg; base < tk.end; base += 64) {
-    const int cnt = min(64, tk.end - base);
-    const int myu = lane < cnt ? col[base + lane] : 0;
+  for (int base = beg + 64 * first; base < end; base += 64 * step) {
+    const int cnt = min(64, end - base);
+    const int myu = lane < cnt ? a.col[base + lane] : 0;
+    if (G == 1) {
+      for (int jj = 0; jj < cnt; jj += kBatch) {
+        T v[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          const int l = jj + q;   // wave-uniform
+          const int u = __builtin_amdgcn_readlane(myu, l & 63);
+          v[q] = l < cnt ? Yp[static_cast<size_t>(u) * B + c] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) acc += v[q];
+      }
+    } else {
+      // uniform trip count: every lane takes part in each shuffle (a shuffle
+      // from an inactive lane would read 0), the add is predicated instead
+      for (int j0 = 0; j0 < cnt; j0 += G) {
+        const int jj = j0 + gq;
+        const int u = __shfl(myu, jj, 64);
+        if (jj < cnt) acc += Yp[static_cast<size_t>(u) * B + c];
+      }
+    }
+  }
+  return reduce_groups<T, B>(acc);
+}
+
+// Same traversal for the two-hop step: neighbour u contributes 1/d_u to column
+// c when bit c of mask[u] is set (u is a neighbour of source c).
+template <typename T, int B>
+__device__ inline T twohop_pieces(const RowArgs<T>& a, const unsigned long long* __restrict__ mask,
+                                  const unsigned* __restrict__ anymask, int beg, int end,
+                                  int first, int step, int lane, int c, int gq) {
+  constexpr int G = 64 / B;
+  T acc = T(0);
+  for (int base = beg + 64 * first; base < end; base += 64 * step) {
+    const int cnt = min(64, end - base);
+    const int myu = lane < cnt ? a.col[base + lane] : 0;
     // the small bitmap filters out the neighbours no column marks
     const bool hit = lane < cnt && ((anymask[myu >> 5] >> (myu & 31)) & 1u);
     const unsigned long long mym = hit ? mask[myu] : 0ull;
-    const T myw = hit ? inv_deg[myu] : T(0);
+    const T myw = hit ? a.inv_deg[myu] : T(0);
     if (__ballot(hit) == 0ull) continue;
     if (G == 1) {
-      // one row per wave: broadcast each neighbour's mask and weight through
-      // scalar registers
       const int mlo = static_cast<int>(mym & 0xFFFFFFFFull);
       const int mhi = static_cast<int>(mym >> 32);
       for (int jj = 0; jj < cnt; ++jj) {
@@ -146,8 +216,6 @@ __global__ __launch_bounds__(kThreads) void k_twohop(const Task* __restrict__ ta
         if ((mk >> c) & 1ull) acc += bcast(myw, jj);
       }
     } else {
-      // uniform trip count: every lane takes part in each shuffle (a shuffle
-      // from an inactive lane would read 0), the add is predicated instead
       for (int j0 = 0; j0 < cnt; j0 += G) {
         const int jj = j0 + gq;
         const unsigned long long mk = __shfl(mym, jj, 64);
@@ -156,98 +224,98 @@ __global__ __launch_bounds__(kThreads) void k_twohop(const Task* __restrict__ ta
       }
     }
   }
-  acc = reduce_groups<T, B>(acc);
-  if (gq == 0) {
+  return reduce_groups<T, B>(acc);
+}
+
+// Workgroup task: the four waves' sums are added in wave order; a whole row
+// is scaled by 1/d and stored, a giant-row chunk goes to its partial row.
+template <typename T, int B>
+__device__ inline void wg_finish(const RowArgs<T>& a, const Task& tk, T sum, int wave, int lane,
+                                 T* __restrict__ Y) {
+  __shared__ T red[kWavesPerBlock][64];
+  red[wave][lane] = sum;
+  __syncthreads();
+  if (wave == 0 && lane < B) {
+    T tot = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) tot += red[w][lane];
     if (tk.part < 0)
-      Y[static_cast<size_t>(tk.row) * B + c] = acc * inv_deg[tk.row];
+      Y[static_cast<size_t>(tk.row) * B + lane] = tot * a.inv_deg[tk.row];
     else
-      partials[static_cast<size_t>(tk.part) * B + c] = acc;
+      a.partials[static_cast<size_t>(tk.part) * B + lane] = tot;
   }
+}
+
+// ------------------------------------------------------------------ Y2 from masks
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
+                                                     const unsigned long long* __restrict__ mask,
+                                                     const unsigned* __restrict__ anymask,
+                                                     T* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int c = lane % B;
+  const int gq = lane / B;
+  if (static_cast<int>(blockIdx.x) < a.nwg) {
+    const Task tk = a.wg_tasks[blockIdx.x];
+    const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, wave, kWavesPerBlock, lane, c, gq);
+    wg_finish<T, B>(a, tk, sum, wave, lane, Y);
+    return;
+  }
+  const int t = (blockIdx.x - a.nwg) * kWavesPerBlock + wave;
+  if (t >= a.ntasks) return;
+  const Task tk = a.tasks[t];
+  const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, 0, 1, lane, c, gq);
+  if (gq == 0) Y[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
 }
 
 // ------------------------------------------------------------------ dense propagation
+// Workgroups [0, nwg): heavy rows and giant-row chunks; then wave tasks; then
+// the accumulation of the step held in Yp (fused, saves a launch).
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_propagate(const Task* __restrict__ tasks,
-                                                        int ntasks,
-                                                        const int32_t* __restrict__ col,
-                                                        const T* __restrict__ inv_deg,
-                                                        const T* __restrict__ Yp,
-                                                        T* __restrict__ Yn,
-                                                        T* __restrict__ partials) {
-  constexpr int G = 64 / B;
+__global__ __launch_bounds__(kThreads) void k_propagate(RowArgs<T> a, const T* __restrict__ Yp,
+                                                        T* __restrict__ Yn) {
+  if (static_cast<int>(blockIdx.x) >= a.row_blocks) {
+    const int k = a.acc.kbeg + (blockIdx.x - a.row_blocks) * kThreads + threadIdx.x;
+    accumulate_slot<T, B>(a, Yp, k);
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (t >= ntasks) return;
-  const Task tk = tasks[t];
+  const int wave = threadIdx.x >> 6;
   const int c = lane % B;
   const int gq = lane / B;
-  T acc = T(0);
-  for (int base = tk.beg; base < tk.end; base += 64) {
-    const int cnt = min(64, tk.end - base);
-    const int myu = lane < cnt ? col[base + lane] : 0;
-    if (G == 1) {
-      int jj = 0;
-      for (; jj + 8 <= cnt; jj += 8) {
-        T v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int u = __builtin_amdgcn_readlane(myu, jj + q);
-          v[q] = Yp[static_cast<size_t>(u) * B + c];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc += v[q];
-      }
-      for (; jj < cnt; ++jj) {
-        const int u = __builtin_amdgcn_readlane(myu, jj);
-        acc += Yp[static_cast<size_t>(u) * B + c];
-      }
-    } else {
-      for (int j0 = 0; j0 < cnt; j0 += G) {   // uniform trip count, see k_twohop
-        const int jj = j0 + gq;
-        const int u = __shfl(myu, jj, 64);
-        if (jj < cnt) acc += Yp[static_cast<size_t>(u) * B + c];
-      }
-    }
+  if (static_cast<int>(blockIdx.x) < a.nwg) {
+    const Task tk = a.wg_tasks[blockIdx.x];
+    const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, wave, kWavesPerBlock, lane, c, gq);
+    wg_finish<T, B>(a, tk, sum, wave, lane, Yn);
+    return;
   }
-  acc = reduce_groups<T, B>(acc);
-  if (gq == 0) {
-    if (tk.part < 0)
-      Yn[static_cast<size_t>(tk.row) * B + c] = acc * inv_deg[tk.row];
-    else
-      partials[static_cast<size_t>(tk.part) * B + c] = acc;
-  }
+  const int t = (blockIdx.x - a.nwg) * kWavesPerBlock + wave;
+  if (t >= a.ntasks) return;
+  const Task tk = a.tasks[t];
+  const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, 0, 1, lane, c, gq);
+  if (gq == 0) Yn[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
 }
 
+// Giant rows: Y[row] = inv_deg[row] * (sum of the chunk partials in chunk order).
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_fixup(const HeavyRow* __restrict__ heavy,
-                                                    int nheavy, const T* __restrict__ inv_deg,
+__global__ __launch_bounds__(kThreads) void k_fixup(const HeavyRow* __restrict__ giant, int ngiant,
+                                                    const T* __restrict__ inv_deg,
                                                     const T* __restrict__ partials,
                                                     T* __restrict__ Y) {
   const int lane = threadIdx.x & 63;
   const int h = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (h >= nheavy || lane >= B) return;
-  const HeavyRow hr = heavy[h];
+  if (h >= ngiant || lane >= B) return;
+  const HeavyRow hr = giant[h];
   T acc = T(0);
   for (int p = 0; p < hr.nparts; ++p) acc += partials[static_cast<size_t>(hr.part0 + p) * B + lane];
   Y[static_cast<size_t>(hr.row) * B + lane] = acc * inv_deg[hr.row];
 }
 
-// ------------------------------------------------------------------ per-step accumulation (Eq. 9)
+// standalone accumulation (the last step of a block)
 template <typename T, int B>
-__global__ void k_accumulate(int kbeg, int kend, int s0, int ell,
-                             const int32_t* __restrict__ slot_row,
-                             const int32_t* __restrict__ col, const double* __restrict__ inv_deg,
-                             const T* __restrict__ Y, const int32_t* __restrict__ tau,
-                             double* __restrict__ gacc) {
-  const int k = kbeg + blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kend) return;
-  if (ell > tau[k]) return;
-  const int s = slot_row[k];
-  const int c = s - s0;
-  const int j = col[k];
-  const double pss = static_cast<double>(Y[static_cast<size_t>(s) * B + c]);
-  const double pjs = static_cast<double>(Y[static_cast<size_t>(j) * B + c]);
-  gacc[k] += (pss - pjs) * inv_deg[s];
+__global__ void k_accumulate(RowArgs<T> a, const T* __restrict__ Y) {
+  accumulate_slot<T, B>(a, Y, a.acc.kbeg + blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ combine and traces
@@ -332,19 +400,21 @@ hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, i
   return hipGetLastError();
 }
 
-hipError_t launch_mask_set(const DeviceGraph& g, int s0, int B, unsigned long long* mask,
-                           unsigned* anymask, bool clear, hipStream_t st) {
-  k_mask_set<<<grid_for(B, kWavesPerBlock), kThreads, 0, st>>>(g.n, s0, B, g.rowptr, g.col, mask,
-                                                               anymask, clear ? 1 : 0);
+hipError_t launch_mask_update(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
+                              unsigned long long* mask, unsigned* anymask, hipStream_t st) {
+  const int64_t mwords = g.n;
+  const int64_t awords = (g.n + 31) / 32;
+  k_mask_update<<<grid_for(2 * B, kWavesPerBlock), kThreads, 0, st>>>(
+      g.n, s_set, s_clear, B, buf, mwords, awords, g.rowptr, g.col, mask, anymask);
   return hipGetLastError();
 }
 
-#define SC_DISPATCH_B(B, CALL)             \
-  switch (B) {                             \
-    case 64: { constexpr int kB = 64; CALL; } break; \
-    case 32: { constexpr int kB = 32; CALL; } break; \
-    case 16: { constexpr int kB = 16; CALL; } break; \
-    default: return hipErrorInvalidValue;  \
+#define SC_DISPATCH_B(B, CALL)                        \
+  switch (B) {                                        \
+    case 64: { constexpr int kB = 64; CALL; } break;  \
+    case 32: { constexpr int kB = 32; CALL; } break;  \
+    case 16: { constexpr int kB = 16; CALL; } break;  \
+    default: return hipErrorInvalidValue;             \
   }
 
 template <typename T>
@@ -355,35 +425,63 @@ template <>
 const double* inv_deg_of<double>(const DeviceGraph& g) { return g.inv_deg_d; }
 
 template <typename T>
-hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
-                         const unsigned* anymask, T* Y, T* partials, hipStream_t st) {
-  SC_DISPATCH_B(B, (k_twohop<T, kB><<<grid_for(g.ntasks, kWavesPerBlock), kThreads, 0, st>>>(
-                        g.tasks, g.ntasks, g.col, inv_deg_of<T>(g), mask, anymask, Y, partials)));
-  return hipGetLastError();
+RowArgs<T> row_args(const DeviceGraph& g, T* partials, const AccJob& acc) {
+  RowArgs<T> a;
+  a.tasks = g.tasks;
+  a.ntasks = g.ntasks;
+  a.wg_tasks = g.wg_tasks;
+  a.nwg = g.nwg;
+  a.row_blocks = g.nwg + static_cast<int>(grid_for(g.ntasks, kWavesPerBlock));
+  a.col = g.col;
+  a.inv_deg = inv_deg_of<T>(g);
+  a.partials = partials;
+  a.slot_row = g.slot_row;
+  a.inv_deg_d = g.inv_deg_d;
+  a.acc = acc;
+  return a;
 }
 
-template <typename T>
-hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                            hipStream_t st) {
-  SC_DISPATCH_B(B, (k_propagate<T, kB><<<grid_for(g.ntasks, kWavesPerBlock), kThreads, 0, st>>>(
-                        g.tasks, g.ntasks, g.col, inv_deg_of<T>(g), Yp, Yn, partials)));
-  return hipGetLastError();
+inline int acc_blocks(const AccJob& acc) {
+  return acc.gacc && acc.kend > acc.kbeg ? static_cast<int>(grid_for(acc.kend - acc.kbeg, kThreads))
+                                          : 0;
 }
 
 template <typename T>
 hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st) {
-  if (g.nheavy == 0) return hipSuccess;
-  SC_DISPATCH_B(B, (k_fixup<T, kB><<<grid_for(g.nheavy, kWavesPerBlock), kThreads, 0, st>>>(
-                        g.heavy, g.nheavy, inv_deg_of<T>(g), partials, Y)));
+  if (g.ngiant == 0) return hipSuccess;
+  SC_DISPATCH_B(B, (k_fixup<T, kB><<<grid_for(g.ngiant, kWavesPerBlock), kThreads, 0, st>>>(
+                        g.giant, g.ngiant, inv_deg_of<T>(g), partials, Y)));
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_accumulate(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
-                             const T* Y, const int32_t* tau_slot, double* gacc, hipStream_t st) {
-  if (kend <= kbeg) return hipSuccess;
-  SC_DISPATCH_B(B, (k_accumulate<T, kB><<<grid_for(kend - kbeg, 256), 256, 0, st>>>(
-                        kbeg, kend, s0, ell, g.slot_row, g.col, g.inv_deg_d, Y, tau_slot, gacc)));
+hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
+                         const unsigned* anymask, T* Y, T* partials, hipStream_t st) {
+  const RowArgs<T> a = row_args<T>(g, partials, AccJob{});
+  SC_DISPATCH_B(B, (k_twohop<T, kB><<<a.row_blocks, kThreads, 0, st>>>(a, mask, anymask, Y)));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fixup<T>(g, B, partials, Y, st);
+}
+
+template <typename T>
+hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
+                            const AccJob& acc, hipStream_t st) {
+  const RowArgs<T> a = row_args<T>(g, partials, acc);
+  const int blocks = a.row_blocks + acc_blocks(acc);
+  SC_DISPATCH_B(B, (k_propagate<T, kB><<<blocks, kThreads, 0, st>>>(a, Yp, Yn)));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fixup<T>(g, B, partials, Yn, st);
+}
+
+template <typename T>
+hipError_t launch_accumulate(const DeviceGraph& g, int B, const T* Y, const AccJob& acc,
+                             hipStream_t st) {
+  const int blocks = acc_blocks(acc);
+  if (blocks == 0) return hipSuccess;
+  const RowArgs<T> a = row_args<T>(g, nullptr, acc);
+  SC_DISPATCH_B(B, (k_accumulate<T, kB><<<blocks, kThreads, 0, st>>>(a, Y)));
   return hipGetLastError();
 }
 
@@ -426,16 +524,12 @@ template hipError_t launch_twohop<float>(const DeviceGraph&, int, const unsigned
 template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigned long long*,
                                           const unsigned*, double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,
-                                            float*, hipStream_t);
+                                            float*, const AccJob&, hipStream_t);
 template hipError_t launch_propagate<double>(const DeviceGraph&, int, const double*, double*,
-                                             double*, hipStream_t);
-template hipError_t launch_fixup<float>(const DeviceGraph&, int, const float*, float*,
-                                        hipStream_t);
-template hipError_t launch_fixup<double>(const DeviceGraph&, int, const double*, double*,
-                                         hipStream_t);
-template hipError_t launch_accumulate<float>(const DeviceGraph&, int, int, int, int, int,
-                                             const float*, const int32_t*, double*, hipStream_t);
-template hipError_t launch_accumulate<double>(const DeviceGraph&, int, int, int, int, int,
-                                              const double*, const int32_t*, double*, hipStream_t);
+                                             double*, const AccJob&, hipStream_t);
+template hipError_t launch_accumulate<float>(const DeviceGraph&, int, const float*,
+                                             const AccJob&, hipStream_t);
+template hipError_t launch_accumulate<double>(const DeviceGraph&, int, const double*,
+                                              const AccJob&, hipStream_t);
 
 }  // namespace sc

@@ -44,7 +44,8 @@ void sc_graph::release() {
   dev_free(d.inv_deg_f);
   dev_free(d.inv_deg_d);
   dev_free(d.tasks);
-  dev_free(d.heavy);
+  dev_free(d.wg_tasks);
+  dev_free(d.giant);
   if (Y[0]) (void)hipFree(Y[0]);
   if (Y[1]) (void)hipFree(Y[1]);
   Y[0] = Y[1] = nullptr;
@@ -178,22 +179,25 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
     if (!odd_cycle) return fail(SC_EBIPARTITE, "graph is bipartite");
   }
 
-  // propagation tasks: chunks of heavy rows first, then whole rows
-  std::vector<sc::Task> tasks;
-  std::vector<sc::HeavyRow> heavy;
+  // gather tasks: workgroup tasks (heavy rows, giant-row chunks) first, then
+  // wave tasks for the light rows
+  std::vector<sc::Task> tasks, wg_tasks;
+  std::vector<sc::HeavyRow> giant;
   int32_t nparts = 0;
   for (int32_t x = 0; x < N; ++x) {
-    if (deg[x] > sc::kChunk) {
+    if (deg[x] > sc::kGiant) {
       sc::HeavyRow hr{x, nparts, 0, 0};
-      for (int32_t b = rowptr[x]; b < rowptr[x + 1]; b += sc::kChunk) {
-        tasks.push_back({x, b, std::min(b + sc::kChunk, rowptr[x + 1]), nparts++});
+      for (int32_t b = rowptr[x]; b < rowptr[x + 1]; b += sc::kGiantChunk) {
+        wg_tasks.push_back({x, b, std::min(b + sc::kGiantChunk, rowptr[x + 1]), nparts++});
         ++hr.nparts;
       }
-      heavy.push_back(hr);
+      giant.push_back(hr);
+    } else if (deg[x] > sc::kChunk) {
+      wg_tasks.push_back({x, rowptr[x], rowptr[x + 1], -1});
+    } else {
+      tasks.push_back({x, rowptr[x], rowptr[x + 1], -1});
     }
   }
-  for (int32_t x = 0; x < N; ++x)
-    if (deg[x] <= sc::kChunk) tasks.push_back({x, rowptr[x], rowptr[x + 1], -1});
 
   std::vector<float> inv_f(N);
   std::vector<double> inv_d(N);
@@ -209,7 +213,8 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   g->d.m = m;
   g->d.nslots = S;
   g->d.ntasks = static_cast<int32_t>(tasks.size());
-  g->d.nheavy = static_cast<int32_t>(heavy.size());
+  g->d.nwg = static_cast<int32_t>(wg_tasks.size());
+  g->d.ngiant = static_cast<int32_t>(giant.size());
   g->d.nparts = nparts;
   auto up = [&](auto** dst, const auto& src) -> hipError_t {
     hipError_t e = dev_alloc(dst, src.size());
@@ -227,7 +232,8 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   if (e == hipSuccess) e = up(&g->d.inv_deg_f, inv_f);
   if (e == hipSuccess) e = up(&g->d.inv_deg_d, inv_d);
   if (e == hipSuccess) e = up(&g->d.tasks, tasks);
-  if (e == hipSuccess) e = up(&g->d.heavy, heavy);
+  if (e == hipSuccess) e = up(&g->d.wg_tasks, wg_tasks);
+  if (e == hipSuccess) e = up(&g->d.giant, giant);
   if (e != hipSuccess) {
     g->release();
     delete g;
@@ -492,10 +498,11 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
     g->pbytes = pb;
   }
   if (!g->mask) {
-    HIP_TRY(dev_alloc(&g->mask, n));
-    HIP_TRY(hipMemset(g->mask, 0, n * sizeof(unsigned long long)));
-    HIP_TRY(dev_alloc(&g->anymask, (n + 31) / 32));
-    HIP_TRY(hipMemset(g->anymask, 0, (n + 31) / 32 * sizeof(unsigned)));
+    HIP_TRY(dev_alloc(&g->mask, 2 * n));
+    HIP_TRY(hipMemset(g->mask, 0, 2 * n * sizeof(unsigned long long)));
+    HIP_TRY(dev_alloc(&g->anymask, 2 * ((n + 31) / 32)));
+    HIP_TRY(hipMemset(g->anymask, 0, 2 * ((n + 31) / 32) * sizeof(unsigned)));
+    g->mask_pending_s0 = -1;
   }
   if (!g->gacc) HIP_TRY(dev_alloc(&g->gacc, S));
   if (!g->tau_slot) HIP_TRY(dev_alloc(&g->tau_slot, S));
@@ -644,6 +651,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     const int lend = plus ? std::min(tmax, tilde) : tmax;
     rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc);
     if (rc) return rc;
+    rc = R.flush_acc();
+    if (rc) return rc;
     if (plus && tmax > tilde) {
       if (tilde < 2) {
         rc = R.init_low(s0, tilde);
@@ -656,6 +665,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
                                   g->tau_slot, g->nr_slot, g->gacc, st));
     }
   }
+  rc = R.flush_masks();
+  if (rc) return rc;
   double* out_dev = dev_ptrs ? out_user : g->out_dev;
   HIP_TRY(sc::launch_combine(g->d, g->gacc, out_dev, st));
   HIP_TRY(hipEventRecord(t1, st));

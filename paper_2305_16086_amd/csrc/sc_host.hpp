@@ -48,8 +48,11 @@ struct sc_graph {
   size_t ybytes = 0;
   void* partials = nullptr;
   size_t pbytes = 0;
-  unsigned long long* mask = nullptr;
-  unsigned* anymask = nullptr;   // one bit per node
+  unsigned long long* mask = nullptr;   // 2 x n words (two alternating buffers)
+  unsigned* anymask = nullptr;          // 2 x ceil(n/32) words, one bit per node
+  int mask_pending_s0 = -1;             // block whose bits are still set
+  int mask_pending_buf = 0;
+  int mask_pending_B = 0;
   double* gacc = nullptr;
   int32_t* tau_slot = nullptr;
   int32_t* tau_row = nullptr;
@@ -138,26 +141,67 @@ struct Runner {
   // written once, the CSR column array, the task list and the degree vector
   double step_bytes() const {
     const double n = g->d.n, S = static_cast<double>(g->rowptr_h[g->d.n]);
-    return 2.0 * n * B * sizeof(T) + 4.0 * S + 16.0 * g->d.ntasks + sizeof(T) * n;
+    return 2.0 * n * B * sizeof(T) + 4.0 * S + 16.0 * (g->d.ntasks + g->d.nwg) + sizeof(T) * n;
   }
 
-  int after_step(int s0, int kbeg, int kend, int ell, bool acc, double* gacc) {
-    if (acc)
-      HIP_TRY(launch_accumulate<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), g->tau_slot, gacc, st));
+  AccJob pending_acc;     // accumulation of the latest step, not yet launched
+
+  int record_step(int s0, int kbeg, int kend, int ell) {
     if (rdiag && ell <= record_to)
       HIP_TRY(launch_record<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), rdiag, roff, st));
     return SC_OK;
   }
 
-  // traverse the block from l = 2 up to l = lend (l = 0, 1 are closed form)
+  // launches the pending accumulation on its own
+  int flush_acc() {
+    if (pending_acc.gacc) HIP_TRY(launch_accumulate<T>(g->d, B, Yb(cur), pending_acc, st));
+    pending_acc = AccJob{};
+    return SC_OK;
+  }
+
+  // clears the neighbour bits a traversal left set
+  int flush_masks() {
+    if (g->mask_pending_s0 >= 0) {
+      HIP_TRY(launch_mask_update(g->d, -1, g->mask_pending_s0, g->mask_pending_B,
+                                 1 - g->mask_pending_buf, g->mask, g->anymask, st));
+      g->mask_pending_s0 = -1;
+    }
+    return SC_OK;
+  }
+
+  // traverse the block from l = 2 up to l = lend (l = 0, 1 are closed form);
+  // the accumulation of step l rides on the launch of step l + 1, the last one
+  // stays pending (flush_acc or a fused consumer launches it)
   int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc) {
+    pending_acc = AccJob{};
     if (lend < 2) return SC_OK;
-    HIP_TRY(launch_mask_set(g->d, s0, B, g->mask, g->anymask, false, st));
+    const int buf = g->mask_pending_s0 >= 0 ? 1 - g->mask_pending_buf : 0;
+    if (g->mask_pending_s0 >= 0 && g->mask_pending_B != B) {
+      int rc0 = flush_masks();
+      if (rc0) return rc0;
+    }
+    HIP_TRY(launch_mask_update(g->d, s0, g->mask_pending_s0, B, buf, g->mask, g->anymask, st));
+    g->mask_pending_s0 = s0;
+    g->mask_pending_buf = buf;
+    g->mask_pending_B = B;
+    unsigned long long* mk = g->mask + static_cast<size_t>(buf) * g->d.n;
+    unsigned* am = g->anymask + static_cast<size_t>(buf) * ((g->d.n + 31) / 32);
     cur = 0;
-    HIP_TRY(launch_twohop<T>(g->d, B, g->mask, g->anymask, Yb(cur), parts(), st));
-    HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(cur), st));
-    HIP_TRY(launch_mask_set(g->d, s0, B, g->mask, g->anymask, true, st));
-    int rc = after_step(s0, kbeg, kend, 2, acc, gacc);
+    HIP_TRY(launch_twohop<T>(g->d, B, mk, am, Yb(cur), parts(), st));
+    auto job = [&](int ell) {
+      AccJob j;
+      if (acc) {
+        j.kbeg = kbeg;
+        j.kend = kend;
+        j.s0 = s0;
+        j.ell = ell;
+        j.tau = g->tau_slot;
+        j.gacc = gacc;
+      }
+      return j;
+    };
+    pending_acc = job(2);
+    int rc = record_step(s0, kbeg, kend, 2);
     if (rc) return rc;
     for (int ell = 3; ell <= lend; ++ell) {
       hipEvent_t a = nullptr, b = nullptr;
@@ -166,13 +210,13 @@ struct Runner {
         if (rc) return rc;
         HIP_TRY(hipEventRecord(a, st));
       }
-      HIP_TRY(launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), st));
+      HIP_TRY(launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st));
       if (timing) HIP_TRY(hipEventRecord(b, st));
       ++stats.prop_launches;
       stats.prop_bytes += step_bytes();
-      HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
       cur = 1 - cur;
-      rc = after_step(s0, kbeg, kend, ell, acc, gacc);
+      pending_acc = job(ell);
+      rc = record_step(s0, kbeg, kend, ell);
       if (rc) return rc;
     }
     return SC_OK;

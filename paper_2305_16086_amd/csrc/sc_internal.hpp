@@ -12,10 +12,13 @@
 
 namespace sc {
 
-// Rows of the CSR are cut into "tasks" of at most kChunk slots.  A row with
-// more slots than kChunk is split into several tasks whose partial sums are
-// combined by a fix-up pass in a fixed order (deterministic, no atomics).
+// Row tasks of the gather kernels: a row with at most kChunk slots is one
+// wave's task, a row with up to kGiant slots one workgroup's task, and a
+// giant row is cut into workgroup chunks of kGiantChunk slots whose partial
+// sums a fix-up pass adds in chunk order (deterministic, no atomics).
 constexpr int kChunk = 256;
+constexpr int kGiant = 4096;
+constexpr int kGiantChunk = 1024;
 constexpr int kWavesPerBlock = 4;     // 256-thread workgroups
 constexpr int kMaxGamma = 16;         // candidate lists kept in registers
 
@@ -40,6 +43,14 @@ struct ColStats {
   double maxN, minN;     // max / min over N(s_c)
 };
 
+// Per-edge accumulation job of one source block: slots [kbeg, kend) of the
+// block starting at s0 gain the step-ell term (gacc == nullptr: no job).
+struct AccJob {
+  int kbeg = 0, kend = 0, s0 = 0, ell = 0;
+  const int32_t* tau = nullptr;
+  double* gacc = nullptr;
+};
+
 struct DeviceGraph {
   int32_t n = 0;
   int64_t m = 0;                 // input edges (halves 0..2m-1)
@@ -52,10 +63,12 @@ struct DeviceGraph {
   int32_t* half_slot = nullptr;  // [2m] half id -> slot
   float* inv_deg_f = nullptr;    // [n]
   double* inv_deg_d = nullptr;   // [n]
-  Task* tasks = nullptr;         // [ntasks] heavy chunks first, then whole rows
+  Task* tasks = nullptr;         // [ntasks] wave tasks: rows with <= kChunk slots
   int32_t ntasks = 0;
-  HeavyRow* heavy = nullptr;     // [nheavy]
-  int32_t nheavy = 0;
+  Task* wg_tasks = nullptr;      // [nwg] workgroup tasks: heavy rows, giant-row chunks
+  int32_t nwg = 0;
+  HeavyRow* giant = nullptr;     // [ngiant] rows cut into chunks
+  int32_t ngiant = 0;
   int32_t nparts = 0;            // total partial rows
 };
 
@@ -74,28 +87,26 @@ hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int i
 hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
                       int32_t* tau_slot, int32_t* tau_row, hipStream_t st);
 
-// Source block [s0, s0+B): mark bit c of mask[u] for every u in N(s0+c).
-hipError_t launch_mask_set(const DeviceGraph& g, int s0, int B, unsigned long long* mask,
-                           unsigned* anymask, bool clear, hipStream_t st);
+// Mark block s_set's neighbour bits in mask buffer `buf` and clear block
+// s_clear's bits (s_clear < 0: none) in the other buffer.  mask: 2 x n words,
+// anymask: 2 x ceil(n/32) words.
+hipError_t launch_mask_update(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
+                              unsigned long long* mask, unsigned* anymask, hipStream_t st);
 
 // Y2 = P P Y0 for the indicator block via the neighbour masks.
 template <typename T>
 hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
                          const unsigned* anymask, T* Y, T* partials, hipStream_t st);
 
-// Yn = P Yp (dense block gather), chunked rows write partial sums.
+// Yn = P Yp (dense block gather); `acc` (may be empty) accumulates the step in Yp.
 template <typename T>
 hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                            hipStream_t st);
+                            const AccJob& acc, hipStream_t st);
 
-// Heavy rows: Y[row] = inv_deg[row] * sum of partials, in chunk order.
+// gacc[k] += (Y[s][c] - Y[j][c]) / d_s for the job's slots with l <= tau_k.
 template <typename T>
-hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
-
-// gacc[k] += (Y[s][c] - Y[j][c]) / d_s for the block's slots with l <= tau_k.
-template <typename T>
-hipError_t launch_accumulate(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
-                             const T* Y, const int32_t* tau_slot, double* gacc, hipStream_t st);
+hipError_t launch_accumulate(const DeviceGraph& g, int B, const T* Y, const AccJob& acc,
+                             hipStream_t st);
 
 // Algorithm 3 summary per column of the block (top-gamma, rho bound, extremes).
 // scratch: kColScratchBytes of device memory.

@@ -292,6 +292,10 @@ int record_and_features(sc_graph* g, int B, hipStream_t st, double lam, float* X
     const int rc = R.traverse(s0b, kbeg, kend, sc::kRecSteps, false, nullptr);
     if (rc) return rc;
   }
+  {
+    const int rc = R.flush_masks();
+    if (rc) return rc;
+  }
   R.rdiag = nullptr;
   R.roff = nullptr;
   HIP_TRY(sc::launch_features<T>(g->d, static_cast<const T*>(g->rdiag), static_cast<const T*>(g->roff),
@@ -381,7 +385,11 @@ int learned_t(sc_graph* g, double eps, const sc_options& o, double* out_user, sc
       Lmax = std::max(Lmax, tmax);
       rc = R.traverse(s0b, kbeg, kend, tmax, true, g->gacc);
       if (rc) return rc;
+      rc = R.flush_acc();
+      if (rc) return rc;
     }
+    rc = R.flush_masks();
+    if (rc) return rc;
     HIP_TRY(sc::launch_combine_masked(g->d, g->gacc, g->fb, out_dev, st));
   }
   HIP_TRY(hipEventRecord(t1, st));

@@ -237,3 +237,22 @@ def test_ba_100k_tgt_plus_sampled(sc):
     srcs = np.unique(np.concatenate([u[sub], v[sub]]))
     _, _, ref = otgt.tgt_plus_replay(G, tau, tt, nr[:m], nr[m:], seed=0x5C5C, sources=srcs)
     np.testing.assert_allclose(out[sub], ref[sub], atol=FP32_TOL, rtol=0)
+
+
+@pytest.mark.parametrize("precision,block", [(1, 64), (0, 64), (0, 16)])
+def test_giant_and_heavy_rows(sc, precision, block):
+    """A hub with 5,500 neighbours (cut into workgroup chunks and a fix-up
+    pass) and hubs with a few hundred (one workgroup each)."""
+    n0, u0, v0 = gg.tree_plus_gnp(6000, 6.0, 17)
+    rng = np.random.default_rng(5)
+    hub = 6000
+    spokes = rng.choice(6000, size=5500, replace=False)
+    mids = [(6001 + k, rng.choice(6000, size=300 + 40 * k, replace=False)) for k in range(3)]
+    u = np.concatenate([u0, np.full(5500, hub)] + [np.full(len(t), h) for h, t in mids])
+    v = np.concatenate([v0, spokes] + [t for _, t in mids])
+    graph = (6004,) + gg.canonical_edges(6004, u, v)
+    d = gg.degrees(*graph)
+    assert d.max() > 4096 and np.sum((d > 256) & (d <= 4096)) >= 3
+    out, _, tau, _, _ = run(sc, graph, 0.1, 5, method=sc.SC_TGT, precision=precision, block=block)
+    ref = otgt.truncated_sc(otgt.Graph(*graph), tau)
+    np.testing.assert_allclose(out, ref, atol=FP64_TOL if precision else FP32_TOL, rtol=0)
