@@ -80,13 +80,14 @@ __device__ inline void list_last(const double (&lv)[kMaxGamma], const int (&li)[
 //     and register themselves with the column;
 //  D  per column: merge the registered lists, test candidate pairs for edges
 //     (Algorithm 3 lines 3-5, safe reading), extremes over N(s).
-// Partial p of column c: pmx/pmn[p*B + c], lists pv/pi[(p*B + c)*gamma + r].
+// Chunk p of column c: pmx/pmn[c*kColParts + p], lists pv/pi[(p*B + c)*gamma + r].
 
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part,
+__global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part, int nparts,
                                                      const T* __restrict__ Y,
                                                      T* __restrict__ pmx, T* __restrict__ pmn) {
   constexpr int G = 64 / B;
+  __shared__ T smx[kThreads], smn[kThreads];
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int c = lane % B;
@@ -107,9 +108,17 @@ __global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part,
       }
     }
   }
-  const size_t o = static_cast<size_t>(part) * B + c;
-  pmx[o] = mx;
-  pmn[o] = mn;
+  // entry (local part pl, column c) sits at pl * B + c == threadIdx.x; store
+  // column-major so each column's chunk values are contiguous
+  smx[threadIdx.x] = mx;
+  smn[threadIdx.x] = mn;
+  __syncthreads();
+  constexpr int kParts = kWavesPerBlock * G;   // parts of this workgroup
+  const int cc = threadIdx.x / kParts;
+  const int pl = threadIdx.x % kParts;
+  const int p0 = blockIdx.x * kParts;
+  pmx[static_cast<size_t>(cc) * nparts + p0 + pl] = smx[pl * B + cc];
+  pmn[static_cast<size_t>(cc) * nparts + p0 + pl] = smn[pl * B + cc];
 }
 
 // one wave per column
@@ -122,15 +131,19 @@ __global__ __launch_bounds__(64) void k_colthresh(int gamma, int nparts, const T
   const int lane = threadIdx.x;
   double v[kPer];
   double mx = -DBL_MAX, mn = DBL_MAX;
+  double w[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {   // all loads issued before any use
+    const int p = lane + 64 * k;
+    const size_t o = static_cast<size_t>(c) * nparts + (p < nparts ? p : 0);
+    v[k] = p < nparts ? static_cast<double>(pmx[o]) : -1.0;
+    w[k] = p < nparts ? static_cast<double>(pmn[o]) : 2.0;
+  }
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int p = lane + 64 * k;
-    const size_t o = static_cast<size_t>(p) * B + c;
-    v[k] = p < nparts ? static_cast<double>(pmx[o]) : -1.0;
-    if (v[k] >= 0.0) {
-      mx = fmax(mx, v[k]);
-      mn = fmin(mn, static_cast<double>(pmn[o]));
-    }
+    // empty chunks carry max -1 and min 2, outside [0, 1]
+    mx = fmax(mx, v[k]);
+    mn = fmin(mn, w[k]);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -193,7 +206,8 @@ __global__ __launch_bounds__(kThreads) void k_colscan(int n, int rows_per_part, 
   const int part = wave * G + lane / B;
   const size_t o = static_cast<size_t>(part) * B + c;
   const T th = thr[c];
-  const bool mine = pmx[o] >= th && pmx[o] >= T(0);
+  const T cmax = pmx[static_cast<size_t>(c) * kColParts + part];
+  const bool mine = cmax >= th && cmax >= T(0);
   if (__ballot(mine) == 0ull) return;   // whole wave uniform
   const int x0 = part * rows_per_part;
   const int x1 = mine ? min(n, x0 + rows_per_part) : x0;
@@ -361,8 +375,7 @@ __global__ __launch_bounds__(kThreads) void k_walk_counts(
     int kbeg, int kend, int s0, int tilde, int gamma, double coef, long long nr_cap,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ slot_row, const int32_t* __restrict__ deg, const T* __restrict__ Y,
-    const ColStats* __restrict__ cs, const int32_t* __restrict__ tau, long long* __restrict__ nr,
-    unsigned long long* __restrict__ work) {
+    const ColStats* __restrict__ cs, const int32_t* __restrict__ tau, long long* __restrict__ nr) {
   const int lane = threadIdx.x & 63;
   const int k = kbeg + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (k >= kend) return;
@@ -375,10 +388,21 @@ __global__ __launch_bounds__(kThreads) void k_walk_counts(
   const int c = s - s0;
   const int j = col[k];
   double jmx = -DBL_MAX, jmn = DBL_MAX;
-  for (int kk = rowptr[j] + lane; kk < rowptr[j + 1]; kk += 64) {
-    const double q = static_cast<double>(Y[static_cast<size_t>(col[kk]) * B + c]);
-    jmx = fmax(jmx, q);
-    jmn = fmin(jmn, q);
+  const int je = rowptr[j + 1];
+  for (int kb = rowptr[j] + lane; kb < je; kb += 64 * 8) {
+    int u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = kb + 64 * q < je ? col[kb + 64 * q] : -1;
+    T y[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) y[q] = u[q] >= 0 ? Y[static_cast<size_t>(u[q]) * B + c] : T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (u[q] >= 0) {
+        jmx = fmax(jmx, static_cast<double>(y[q]));
+        jmn = fmin(jmn, static_cast<double>(y[q]));
+      }
+    }
   }
   jmx = wave_max(jmx);
   jmn = wave_min(jmn);
@@ -401,8 +425,37 @@ __global__ __launch_bounds__(kThreads) void k_walk_counts(
   if (!(r >= 1.0)) r = 1.0;
   long long w = r > static_cast<double>(nr_cap) ? nr_cap : static_cast<long long>(r);
   nr[k] = w;
-  atomicAdd(&work[0], static_cast<unsigned long long>(w));
-  atomicAdd(&work[1], static_cast<unsigned long long>(w) * 2ull * static_cast<unsigned long long>(len));
+}
+
+// walk pairs and single-walk steps of slots [kbeg, kend): one atomic pair per
+// workgroup (integer sums, so the totals do not depend on the order)
+__global__ __launch_bounds__(256) void k_work_totals(int kbeg, int kend, int tilde,
+                                                     const int32_t* __restrict__ tau,
+                                                     const long long* __restrict__ nr,
+                                                     unsigned long long* __restrict__ work) {
+  __shared__ unsigned long long s0[256], s1[256];
+  unsigned long long a = 0, b = 0;
+  for (int k = kbeg + blockIdx.x * 256 + threadIdx.x; k < kend; k += gridDim.x * 256) {
+    const long long w = nr[k];
+    if (w > 0) {
+      a += static_cast<unsigned long long>(w);
+      b += static_cast<unsigned long long>(w) * 2ull * static_cast<unsigned long long>(tau[k] - tilde);
+    }
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&work[0], s0[0]);
+    atomicAdd(&work[1], s1[0]);
+  }
 }
 
 // One wave per slot; lanes take walk pairs r = lane, lane + 64, ...
@@ -424,26 +477,26 @@ __global__ __launch_bounds__(kThreads) void k_walks(
   const int j = col[k];
   double acc = 0.0;
   for (long long r = lane; r < n_r; r += 64) {
-    double S[2];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int pos = side == 0 ? s : j;
-      double sum = 0.0;
-      U32x4 words;
-      for (int t = 0; t < len; ++t) {
-        if ((t & 3) == 0)
-          words = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
-                                static_cast<uint32_t>(r),
-                                (static_cast<uint32_t>(side) << 31) | static_cast<uint32_t>(t >> 2),
-                                k0, k1);
-        const uint32_t w = words.w[t & 3];
-        const int d = deg[pos];
-        pos = col[rowptr[pos] + static_cast<int>(pick_neighbour(w, static_cast<uint32_t>(d)))];
-        sum += static_cast<double>(Y[static_cast<size_t>(pos) * B + c]);
+    // the two walks of the pair advance in lockstep so their loads overlap
+    int pos0 = s, pos1 = j;
+    double sum0 = 0.0, sum1 = 0.0;
+    U32x4 w0, w1;
+    for (int t = 0; t < len; ++t) {
+      if ((t & 3) == 0) {
+        const uint32_t hi = static_cast<uint32_t>(t >> 2);
+        w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                           static_cast<uint32_t>(r), hi, k0, k1);
+        w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                           static_cast<uint32_t>(r), (1u << 31) | hi, k0, k1);
       }
-      S[side] = sum;
+      const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
+      const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
+      pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[t & 3], static_cast<uint32_t>(e0 - b0)))];
+      pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[t & 3], static_cast<uint32_t>(e1 - b1)))];
+      sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + c]);
+      sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + c]);
     }
-    acc += (S[0] - S[1]) * inv_deg[s];   // X of Eq. 11
+    acc += (sum0 - sum1) * inv_deg[s];   // X of Eq. 11
   }
   acc = wave_sum(acc);
   if (lane == 0) gacc[k] += acc / static_cast<double>(n_r);
@@ -480,8 +533,8 @@ hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const
   int* act = reinterpret_cast<int*>(pmn + cells);             // [64][kColParts]
   int* nact = act + cells;                                     // [64]
   T* thr = reinterpret_cast<T*>(nact + 64);                    // [64]
-  SC_DISPATCH_B(B, (k_colmax<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(g.n, rows, Y,
-                                                                                pmx, pmn)));
+  SC_DISPATCH_B(B, (k_colmax<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(
+                        g.n, rows, nparts, Y, pmx, pmn)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64, 0, st>>>(gamma, nparts, pmx, pmn, thr, nact,
@@ -503,13 +556,23 @@ template <typename T>
 hipError_t launch_walk_counts(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                               int gamma, double coef, int64_t nr_cap, const T* Y,
                               const ColStats* cs, const int32_t* tau_slot, int64_t* nr_slot,
-                              unsigned long long* work, hipStream_t st) {
+                              hipStream_t st) {
   if (kend <= kbeg) return hipSuccess;
   SC_DISPATCH_B(B, (k_walk_counts<T, kB><<<grid_for(kend - kbeg, kWavesPerBlock), kThreads, 0,
                                           st>>>(
                         kbeg, kend, s0, tilde, gamma, coef, static_cast<long long>(nr_cap),
                         g.rowptr, g.col, g.slot_row, g.deg, Y, cs, tau_slot,
-                        reinterpret_cast<long long*>(nr_slot), work)));
+                        reinterpret_cast<long long*>(nr_slot))));
+  return hipGetLastError();
+}
+
+hipError_t launch_work_totals(int kbeg, int kend, int tilde, const int32_t* tau_slot,
+                              const int64_t* nr_slot, unsigned long long* work, hipStream_t st) {
+  if (kend <= kbeg) return hipSuccess;
+  unsigned blocks = grid_for(kend - kbeg, 256);
+  if (blocks > 256) blocks = 256;
+  k_work_totals<<<blocks, 256, 0, st>>>(kbeg, kend, tilde, tau_slot,
+                                        reinterpret_cast<const long long*>(nr_slot), work);
   return hipGetLastError();
 }
 
@@ -533,12 +596,10 @@ template hipError_t launch_colstats<double>(const DeviceGraph&, int, int, int, c
                                             ColStats*, void*, hipStream_t);
 template hipError_t launch_walk_counts<float>(const DeviceGraph&, int, int, int, int, int, int,
                                               double, int64_t, const float*, const ColStats*,
-                                              const int32_t*, int64_t*, unsigned long long*,
-                                              hipStream_t);
+                                              const int32_t*, int64_t*, hipStream_t);
 template hipError_t launch_walk_counts<double>(const DeviceGraph&, int, int, int, int, int, int,
                                                double, int64_t, const double*, const ColStats*,
-                                               const int32_t*, int64_t*, unsigned long long*,
-                                               hipStream_t);
+                                               const int32_t*, int64_t*, hipStream_t);
 template hipError_t launch_walks<float>(const DeviceGraph&, int, int, int, int, int, uint64_t,
                                         const float*, const int32_t*, const int64_t*, double*,
                                         hipStream_t);

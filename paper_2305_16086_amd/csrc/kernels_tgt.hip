@@ -127,8 +127,11 @@ __device__ inline double bcast(double v, int jj) {
 // Pointers the row kernels need (passed by value).
 template <typename T>
 struct RowArgs {
-  const Task* tasks;          // wave tasks (light rows)
+  const Task* tasks;          // wave tasks: one light row each (used when B < 64)
   int ntasks;
+  const Task* ptasks;         // wave tasks: runs of consecutive light rows (B = 64)
+  int nptasks;
+  const int32_t* rowptr;
   const Task* wg_tasks;       // workgroup tasks (heavy rows, giant-row chunks)
   int nwg;
   int row_blocks;             // nwg + workgroups of wave tasks
@@ -227,6 +230,79 @@ __device__ inline T twohop_pieces(const RowArgs<T>& a, const unsigned long long*
   return reduce_groups<T, B>(acc);
 }
 
+// A run of consecutive light rows with at most 64 slots in total (B = 64):
+// one coalesced load of their neighbour lists, all gathers in flight, and the
+// row sums closed in slot order (the same order as the one-row path).
+template <typename T, int B>
+__device__ inline void gather_run(const RowArgs<T>& a, const T* __restrict__ Yp, const Task& tk,
+                                  int lane, T* __restrict__ Yn) {
+  constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;
+  const int nrows = tk.part;
+  const int cnt = tk.end - tk.beg;
+  const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
+  const int myend = lane < nrows ? a.rowptr[tk.row + lane + 1] - tk.beg : 0;
+  const T myinv = lane < nrows ? a.inv_deg[tk.row + lane] : T(0);
+  T acc = T(0);
+  int ri = 0;
+  int bnd = __builtin_amdgcn_readlane(myend, 0);
+  for (int jj = 0; jj < cnt; jj += kBatch) {
+    T v[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int l = jj + q;
+      const int u = __builtin_amdgcn_readlane(myu, l & 63);
+      v[q] = l < cnt ? Yp[static_cast<size_t>(u) * B + lane] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int l = jj + q;
+      if (l < cnt) {
+        acc += v[q];
+        if (l + 1 == bnd) {
+          Yn[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+          acc = T(0);
+          ++ri;
+          bnd = __builtin_amdgcn_readlane(myend, ri & 63);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int B>
+__device__ inline void twohop_run(const RowArgs<T>& a, const unsigned long long* __restrict__ mask,
+                                  const unsigned* __restrict__ anymask, const Task& tk, int lane,
+                                  T* __restrict__ Y) {
+  const int nrows = tk.part;
+  const int cnt = tk.end - tk.beg;
+  const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
+  const int myend = lane < nrows ? a.rowptr[tk.row + lane + 1] - tk.beg : 0;
+  const T myinv = lane < nrows ? a.inv_deg[tk.row + lane] : T(0);
+  const bool hit = lane < cnt && ((anymask[myu >> 5] >> (myu & 31)) & 1u);
+  const unsigned long long mym = hit ? mask[myu] : 0ull;
+  const T myw = hit ? a.inv_deg[myu] : T(0);
+  const unsigned long long hits = __ballot(hit);
+  const int mlo = static_cast<int>(mym & 0xFFFFFFFFull);
+  const int mhi = static_cast<int>(mym >> 32);
+  T acc = T(0);
+  int ri = 0;
+  int bnd = __builtin_amdgcn_readlane(myend, 0);
+  for (int l = 0; l < cnt; ++l) {
+    if ((hits >> l) & 1ull) {
+      const unsigned long long mk =
+          (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readlane(mhi, l))) << 32) |
+          static_cast<unsigned>(__builtin_amdgcn_readlane(mlo, l));
+      if ((mk >> lane) & 1ull) acc += bcast(myw, l);
+    }
+    if (l + 1 == bnd) {
+      Y[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+      acc = T(0);
+      ++ri;
+      bnd = __builtin_amdgcn_readlane(myend, ri & 63);
+    }
+  }
+}
+
 // Workgroup task: the four waves' sums are added in wave order; a whole row
 // is scaled by 1/d and stored, a giant-row chunk goes to its partial row.
 template <typename T, int B>
@@ -263,6 +339,17 @@ __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
     return;
   }
   const int t = (blockIdx.x - a.nwg) * kWavesPerBlock + wave;
+  if (B == 64) {
+    if (t >= a.nptasks) return;
+    const Task tk = a.ptasks[t];
+    if (tk.end - tk.beg <= 64) {
+      twohop_run<T, B>(a, mask, anymask, tk, lane, Y);
+      return;
+    }
+    const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, 0, 1, lane, c, gq);
+    Y[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
+    return;
+  }
   if (t >= a.ntasks) return;
   const Task tk = a.tasks[t];
   const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, 0, 1, lane, c, gq);
@@ -291,6 +378,17 @@ __global__ __launch_bounds__(kThreads) void k_propagate(RowArgs<T> a, const T* _
     return;
   }
   const int t = (blockIdx.x - a.nwg) * kWavesPerBlock + wave;
+  if (B == 64) {
+    if (t >= a.nptasks) return;
+    const Task tk = a.ptasks[t];
+    if (tk.end - tk.beg <= 64) {
+      gather_run<T, B>(a, Yp, tk, lane, Yn);
+      return;
+    }
+    const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, 0, 1, lane, c, gq);
+    Yn[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
+    return;
+  }
   if (t >= a.ntasks) return;
   const Task tk = a.tasks[t];
   const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, 0, 1, lane, c, gq);
@@ -425,13 +523,16 @@ template <>
 const double* inv_deg_of<double>(const DeviceGraph& g) { return g.inv_deg_d; }
 
 template <typename T>
-RowArgs<T> row_args(const DeviceGraph& g, T* partials, const AccJob& acc) {
+RowArgs<T> row_args(const DeviceGraph& g, int B, T* partials, const AccJob& acc) {
   RowArgs<T> a;
   a.tasks = g.tasks;
   a.ntasks = g.ntasks;
+  a.ptasks = g.ptasks;
+  a.nptasks = g.nptasks;
+  a.rowptr = g.rowptr;
   a.wg_tasks = g.wg_tasks;
   a.nwg = g.nwg;
-  a.row_blocks = g.nwg + static_cast<int>(grid_for(g.ntasks, kWavesPerBlock));
+  a.row_blocks = g.nwg + static_cast<int>(grid_for(B == 64 ? g.nptasks : g.ntasks, kWavesPerBlock));
   a.col = g.col;
   a.inv_deg = inv_deg_of<T>(g);
   a.partials = partials;
@@ -457,7 +558,7 @@ hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hi
 template <typename T>
 hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
                          const unsigned* anymask, T* Y, T* partials, hipStream_t st) {
-  const RowArgs<T> a = row_args<T>(g, partials, AccJob{});
+  const RowArgs<T> a = row_args<T>(g, B, partials, AccJob{});
   SC_DISPATCH_B(B, (k_twohop<T, kB><<<a.row_blocks, kThreads, 0, st>>>(a, mask, anymask, Y)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -467,7 +568,7 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 template <typename T>
 hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
                             const AccJob& acc, hipStream_t st) {
-  const RowArgs<T> a = row_args<T>(g, partials, acc);
+  const RowArgs<T> a = row_args<T>(g, B, partials, acc);
   const int blocks = a.row_blocks + acc_blocks(acc);
   SC_DISPATCH_B(B, (k_propagate<T, kB><<<blocks, kThreads, 0, st>>>(a, Yp, Yn)));
   hipError_t e = hipGetLastError();
@@ -480,7 +581,7 @@ hipError_t launch_accumulate(const DeviceGraph& g, int B, const T* Y, const AccJ
                              hipStream_t st) {
   const int blocks = acc_blocks(acc);
   if (blocks == 0) return hipSuccess;
-  const RowArgs<T> a = row_args<T>(g, nullptr, acc);
+  const RowArgs<T> a = row_args<T>(g, B, nullptr, acc);
   SC_DISPATCH_B(B, (k_accumulate<T, kB><<<blocks, kThreads, 0, st>>>(a, Y)));
   return hipGetLastError();
 }

@@ -45,10 +45,18 @@ void sc_graph::release() {
   dev_free(d.inv_deg_d);
   dev_free(d.tasks);
   dev_free(d.wg_tasks);
+  dev_free(d.ptasks);
   dev_free(d.giant);
-  if (Y[0]) (void)hipFree(Y[0]);
-  if (Y[1]) (void)hipFree(Y[1]);
-  Y[0] = Y[1] = nullptr;
+  for (auto& y : Y) {
+    if (y) (void)hipFree(y);
+    y = nullptr;
+  }
+  if (tail_stream) (void)hipStreamDestroy(tail_stream);
+  tail_stream = nullptr;
+  for (auto& e : pipe_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (partials) (void)hipFree(partials);
   partials = nullptr;
   dev_free(mask);
@@ -198,6 +206,20 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
       tasks.push_back({x, rowptr[x], rowptr[x + 1], -1});
     }
   }
+  // runs of consecutive light rows, at most 64 slots per run (rows with more
+  // than 64 slots stay alone)
+  std::vector<sc::Task> ptasks;
+  for (int32_t x = 0; x < N;) {
+    if (deg[x] > sc::kChunk) {
+      ++x;
+      continue;
+    }
+    int32_t y = x + 1;
+    if (deg[x] <= 64)
+      while (y < N && deg[y] <= sc::kChunk && rowptr[y + 1] - rowptr[x] <= 64) ++y;
+    ptasks.push_back({x, rowptr[x], rowptr[y], y - x});
+    x = y;
+  }
 
   std::vector<float> inv_f(N);
   std::vector<double> inv_d(N);
@@ -213,6 +235,7 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   g->d.m = m;
   g->d.nslots = S;
   g->d.ntasks = static_cast<int32_t>(tasks.size());
+  g->d.nptasks = static_cast<int32_t>(ptasks.size());
   g->d.nwg = static_cast<int32_t>(wg_tasks.size());
   g->d.ngiant = static_cast<int32_t>(giant.size());
   g->d.nparts = nparts;
@@ -233,6 +256,7 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   if (e == hipSuccess) e = up(&g->d.inv_deg_d, inv_d);
   if (e == hipSuccess) e = up(&g->d.tasks, tasks);
   if (e == hipSuccess) e = up(&g->d.wg_tasks, wg_tasks);
+  if (e == hipSuccess) e = up(&g->d.ptasks, ptasks);
   if (e == hipSuccess) e = up(&g->d.giant, giant);
   if (e != hipSuccess) {
     g->release();
@@ -480,13 +504,12 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   const int64_t S = static_cast<int64_t>(g->rowptr_h[n]);
   const size_t yb = static_cast<size_t>(n) * B * tsize;
   if (yb > g->ybytes) {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4; ++i) {
       if (g->Y[i]) (void)hipFree(g->Y[i]);
       g->Y[i] = nullptr;
     }
     g->ybytes = 0;
-    HIP_TRY(hipMalloc(&g->Y[0], yb));
-    HIP_TRY(hipMalloc(&g->Y[1], yb));
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipMalloc(&g->Y[i], yb));
     g->ybytes = yb;
   }
   const size_t pb = static_cast<size_t>(std::max(g->d.nparts, 1)) * B * tsize;
@@ -512,6 +535,13 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
   if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
+  return SC_OK;
+}
+
+int ensure_pipeline(sc_graph* g) {
+  if (!g->tail_stream) HIP_TRY(hipStreamCreateWithFlags(&g->tail_stream, hipStreamNonBlocking));
+  for (auto& e : g->pipe_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return SC_OK;
 }
 
@@ -621,8 +651,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
             HIP_TRY(hipMemsetAsync(g->work, 0, 2 * sizeof(unsigned long long), st));
             HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, st));
             HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, ell, gamma, coef, nr_cap,
-                                              R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot,
-                                              g->work, st));
+                                              R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, st));
+            HIP_TRY(sc::launch_work_totals(kbeg, kend, ell, g->tau_slot, g->nr_slot, g->work, st));
             HIP_TRY(hipMemcpyAsync(wk, g->work, sizeof(wk), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
           }
@@ -645,12 +675,29 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
 
   unsigned long long* work = g->work;
   HIP_TRY(hipMemsetAsync(work, 0, 2 * sizeof(unsigned long long), st));
+  // Block pipeline: the traversal of block b runs on the caller's stream, its
+  // tail (last accumulation, candidate summary, walk counts, walks) on the
+  // tail stream, overlapping the traversal of block b+1.  Blocks alternate
+  // between two Y pairs; pair p is reused only after the tail of the block
+  // two back has finished.  Blocks touch disjoint slots of gacc and nr_slot.
+  rc = sc::ensure_pipeline(g);
+  if (rc) return rc;
+  hipStream_t sb = g->tail_stream;
+  HIP_TRY(hipEventRecord(g->pipe_ev[0], st));
+  HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[0], 0));
   for (int b = 0; b < nblocks; ++b) {
     int s0, kbeg, kend, tmax;
     block_range(b, &s0, &kbeg, &kend, &tmax);
     const int lend = plus ? std::min(tmax, tilde) : tmax;
+    const int pair = b & 1;
+    if (b >= 2) HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[3 + pair], 0));
+    R.st = st;
+    R.po = 2 * pair;
     rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc);
     if (rc) return rc;
+    HIP_TRY(hipEventRecord(g->pipe_ev[1 + pair], st));
+    HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[1 + pair], 0));
+    R.st = sb;
     rc = R.flush_acc();
     if (rc) return rc;
     if (plus && tmax > tilde) {
@@ -658,13 +705,18 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
         rc = R.init_low(s0, tilde);
         if (rc) return rc;
       }
-      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, st));
+      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, sb));
       HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
-                                        R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, work, st));
+                                        R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, sb));
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
-                                  g->tau_slot, g->nr_slot, g->gacc, st));
+                                  g->tau_slot, g->nr_slot, g->gacc, sb));
     }
+    HIP_TRY(hipEventRecord(g->pipe_ev[3 + pair], sb));
+    R.st = st;
   }
+  HIP_TRY(hipEventRecord(g->pipe_ev[0], sb));
+  HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[0], 0));
+  R.po = 0;
   rc = R.flush_masks();
   if (rc) return rc;
   double* out_dev = dev_ptrs ? out_user : g->out_dev;
@@ -694,7 +746,11 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       std::memcpy(o.tilde_tau_out, tilde_h.data(), n * sizeof(int32_t));
   }
   unsigned long long wk[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(wk, work, sizeof(wk), hipMemcpyDeviceToHost, st));
+  if (plus) {
+    HIP_TRY(sc::launch_work_totals(0, static_cast<int>(g->d.nslots), tilde, g->tau_slot,
+                                   g->nr_slot, work, st));
+    HIP_TRY(hipMemcpyAsync(wk, work, sizeof(wk), hipMemcpyDeviceToHost, st));
+  }
   if (!dev_ptrs) {
     HIP_TRY(hipMemcpyAsync(out_user, out_dev, m * sizeof(double), hipMemcpyDeviceToHost, st));
     if (o.tau_out)

@@ -44,8 +44,10 @@ struct sc_graph {
   double lambda_star = -1.0;
 
   // work buffers, grown on demand
-  void* Y[2] = {nullptr, nullptr};
+  void* Y[4] = {nullptr, nullptr, nullptr, nullptr};   // two pairs (block pipeline)
   size_t ybytes = 0;
+  hipStream_t tail_stream = nullptr;   // per-block tails overlap the next traversal
+  hipEvent_t pipe_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   void* partials = nullptr;
   size_t pbytes = 0;
   unsigned long long* mask = nullptr;   // 2 x n words (two alternating buffers)
@@ -80,6 +82,7 @@ struct sc_graph {
 namespace sc {
 
 int ensure_buffers(sc_graph* g, int B, size_t tsize);
+int ensure_pipeline(sc_graph* g);
 int ensure_closure_buffers(sc_graph* g, size_t tsize);
 int compute_lambda_star(sc_graph* g, hipStream_t st, double* out);
 int graph_lambda_star(sc_graph* g, hipStream_t st, double* out);
@@ -118,11 +121,12 @@ struct Runner {
   sc_stats stats{};
   size_t ev_used = 0;
   int cur = 0;            // index of the Y buffer holding the latest step
+  int po = 0;             // first buffer of the Y pair in use (0 or 2)
   T* rdiag = nullptr;     // optional per-slot recordings of p_l(s,s), p_l(j,s)
   T* roff = nullptr;
   int record_to = -1;     // record steps 2..record_to
 
-  T* Yb(int i) { return static_cast<T*>(g->Y[i]); }
+  T* Yb(int i) { return static_cast<T*>(g->Y[po + i]); }
   T* parts() { return static_cast<T*>(g->partials); }
 
   int event_pair(hipEvent_t* a, hipEvent_t* b) {

@@ -65,6 +65,8 @@ struct DeviceGraph {
   double* inv_deg_d = nullptr;   // [n]
   Task* tasks = nullptr;         // [ntasks] wave tasks: rows with <= kChunk slots
   int32_t ntasks = 0;
+  Task* ptasks = nullptr;        // [nptasks] wave tasks for B = 64: runs of consecutive light
+  int32_t nptasks = 0;           //   rows with <= 64 slots in total (part = row count)
   Task* wg_tasks = nullptr;      // [nwg] workgroup tasks: heavy rows, giant-row chunks
   int32_t nwg = 0;
   HeavyRow* giant = nullptr;     // [ngiant] rows cut into chunks
@@ -124,8 +126,11 @@ template <typename T>
 hipError_t launch_walk_counts(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                               int gamma,
                               double coef, int64_t nr_cap, const T* Y, const ColStats* cs,
-                              const int32_t* tau_slot, int64_t* nr_slot,
-                              unsigned long long* work /*[2]: walks, steps*/, hipStream_t st);
+                              const int32_t* tau_slot, int64_t* nr_slot, hipStream_t st);
+
+// work[0] += walk pairs, work[1] += single-walk steps over slots [kbeg, kend)
+hipError_t launch_work_totals(int kbeg, int kend, int tilde, const int32_t* tau_slot,
+                              const int64_t* nr_slot, unsigned long long* work, hipStream_t st);
 
 // Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots.
 template <typename T>
