@@ -69,6 +69,7 @@ void sc_graph::release() {
   if (colscratch) (void)hipFree(colscratch);
   colscratch = nullptr;
   dev_free(work);
+  dev_free(plan_work);
   dev_free(out_dev);
   dev_free(tau_out_dev);
   dev_free(nr_out_dev);
@@ -534,6 +535,7 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->cs) HIP_TRY(dev_alloc(&g->cs, 64));
   if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
   if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
+  if (!g->plan_work) HIP_TRY(dev_alloc(&g->plan_work, 2 * 64));
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
   return SC_OK;
 }
@@ -551,17 +553,27 @@ namespace {
 
 using sc::Runner;
 
+// Switch-step cost model.  The traversal of a block runs on the critical
+// stream, its tail (candidate summary, walk counts, walks) on the tail stream,
+// so a block costs about max(traversal, tail) plus an interference share of
+// the shorter one.  Constants are whole-GPU rates measured on MI355X; the
+// environment can override them for tuning.
 struct CostModel {
-  double gather_bw;   // bytes/s for the neighbour gathers of one dense step
-  double step_fixed;  // s of fixed overhead per dense step
-  double walk_step;   // s per single-walk step (whole-GPU throughput)
+  double gather_bw;     // bytes/s of neighbour-row gathers in a dense step
+  double step_fixed;    // s of fixed cost per dense step
+  double twohop_frac;   // two-hop step cost relative to a dense step
+  double tail_fixed;    // s of the candidate summary and walk counts per block
+  double walk_step;     // s per single-walk step
+  double overlap;       // share of the shorter stream that still costs time
 };
 
 CostModel cost_model() {
-  CostModel c{4.0e12, 6.0e-6, 1.0e-10};
+  CostModel c{7.5e12, 3.0e-6, 0.5, 6.0e-5, 3.5e-11, 0.25};
   if (const char* s = std::getenv("SC_COST_GATHER_BW")) c.gather_bw = std::atof(s);
   if (const char* s = std::getenv("SC_COST_STEP_FIXED")) c.step_fixed = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_TAIL_FIXED")) c.tail_fixed = std::atof(s);
   if (const char* s = std::getenv("SC_COST_WALK_STEP")) c.walk_step = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_OVERLAP")) c.overlap = std::atof(s);
   return c;
 }
 
@@ -630,41 +642,59 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     // Eq. 13 constant; m counts distinct edges
     coef = 8.0 * std::log(static_cast<double>(g->d.nslots) / delta) / (eps * eps);
     HIP_TRY(hipMemsetAsync(g->nr_slot, 0, g->rowptr_h[n] * sizeof(int64_t), st));
+    const sc_graph::PlanKey key{eps, L, max_L, lam, B, static_cast<int>(sizeof(T)), gamma, delta};
     if (o.tilde_tau >= 0) {
       tilde = std::min(o.tilde_tau, Lmax);
+    } else if (g->plan_valid && g->plan_key == key) {
+      tilde = g->plan_tilde;   // the switch step depends only on the graph and these options
     } else {
-      // cost model on sample blocks: dense steps vs. walk steps for each switch point
+      // sample blocks: walk steps at every candidate switch point
       const CostModel cm = cost_model();
-      const double dense_step =
-          cm.step_fixed + static_cast<double>(g->rowptr_h[n]) * B * sizeof(T) / cm.gather_bw;
+      const double dense = cm.step_fixed + static_cast<double>(g->d.nslots) * B * sizeof(T) / cm.gather_bw;
       const int nsamp = std::min(nblocks, 4);
       std::vector<double> cost(Lmax + 1, 0.0);
       for (int si = 0; si < nsamp; ++si) {
         const int b = static_cast<int>((si + 0.5) * nblocks / nsamp);
         int s0, kbeg, kend, tmax;
         block_range(b, &s0, &kbeg, &kend, &tmax);
-        for (int ell = 2; ell <= Lmax; ++ell) {
-          unsigned long long wk[2] = {0, 0};
-          if (ell < tmax) {
-            rc = R.traverse(s0, kbeg, kend, ell, false, nullptr);
-            if (rc) return rc;
-            HIP_TRY(hipMemsetAsync(g->work, 0, 2 * sizeof(unsigned long long), st));
+        std::vector<unsigned long long> wk(2 * (Lmax + 1), 0ull);
+        HIP_TRY(hipMemsetAsync(g->plan_work, 0, 2 * 64 * sizeof(unsigned long long), st));
+        if (tmax >= 3) {
+          rc = R.traverse(s0, kbeg, kend, 2, false, nullptr);
+          if (rc) return rc;
+          for (int ell = 2; ell < tmax && ell <= Lmax && ell < 64; ++ell) {
+            if (ell > 2) {
+              rc = R.advance();
+              if (rc) return rc;
+            }
             HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, st));
             HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, ell, gamma, coef, nr_cap,
                                               R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, st));
-            HIP_TRY(sc::launch_work_totals(kbeg, kend, ell, g->tau_slot, g->nr_slot, g->work, st));
-            HIP_TRY(hipMemcpyAsync(wk, g->work, sizeof(wk), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(sc::launch_work_totals(kbeg, kend, ell, g->tau_slot, g->nr_slot,
+                                           g->plan_work + 2 * ell, st));
           }
+          HIP_TRY(hipMemcpyAsync(wk.data(), g->plan_work,
+                                 std::min<size_t>(wk.size(), 2 * 64) * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+        }
+        for (int ell = 2; ell <= Lmax; ++ell) {
           const int steps = std::min(ell, tmax);
-          cost[ell] += (steps >= 2 ? (steps - 1) * dense_step : 0.0) +
-                       static_cast<double>(wk[1]) * cm.walk_step;
+          const double trav = steps >= 2 ? cm.step_fixed + dense * (cm.twohop_frac + (steps - 2)) : 0.0;
+          // switch points beyond the 64 counter slots are not candidates
+          const double tail = ell < tmax ? (ell < 64 ? cm.tail_fixed + static_cast<double>(wk[2 * ell + 1]) * cm.walk_step
+                                                     : 1e30)
+                                         : cm.step_fixed;
+          cost[ell] += std::max(trav, tail) + cm.overlap * std::min(trav, tail);
         }
       }
       tilde = Lmax;
       for (int ell = 2; ell <= Lmax; ++ell)
         if (cost[ell] < cost[tilde]) tilde = ell;
       HIP_TRY(hipMemsetAsync(g->nr_slot, 0, g->rowptr_h[n] * sizeof(int64_t), st));
+      g->plan_key = key;
+      g->plan_tilde = tilde;
+      g->plan_valid = true;
     }
     R.stats.tilde_tau = tilde;
   }

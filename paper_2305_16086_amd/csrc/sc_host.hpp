@@ -62,6 +62,22 @@ struct sc_graph {
   sc::ColStats* cs = nullptr;
   void* colscratch = nullptr;  // sc::kColScratchBytes
   unsigned long long* work = nullptr;
+  unsigned long long* plan_work = nullptr;   // [2 x 64] walk totals per candidate switch step
+  // cached switch-step plan (the cost model depends only on these inputs)
+  struct PlanKey {
+    double eps;
+    int L, max_L;
+    double lam;
+    int B, tsize, gamma;
+    double delta;
+    bool operator==(const PlanKey& o) const {
+      return eps == o.eps && L == o.L && max_L == o.max_L && lam == o.lam && B == o.B &&
+             tsize == o.tsize && gamma == o.gamma && delta == o.delta;
+    }
+  };
+  PlanKey plan_key{};
+  int plan_tilde = -1;
+  bool plan_valid = false;
   double* out_dev = nullptr;
   int32_t* tau_out_dev = nullptr;
   int64_t* nr_out_dev = nullptr;
@@ -223,6 +239,13 @@ struct Runner {
       rc = record_step(s0, kbeg, kend, ell);
       if (rc) return rc;
     }
+    return SC_OK;
+  }
+
+  // one more dense step without accumulation (switch-step planning)
+  int advance() {
+    HIP_TRY(launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), AccJob{}, st));
+    cur = 1 - cur;
     return SC_OK;
   }
 
