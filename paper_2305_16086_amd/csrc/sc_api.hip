@@ -88,10 +88,8 @@ void sc_graph::release() {
 
 // ====================================================================== graph build
 
-extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
-                              unsigned flags, sc_graph** out) {
-  if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
-  *out = nullptr;
+int sc::build_host_csr(int64_t n, int64_t m, const int64_t* u, const int64_t* v, unsigned flags,
+                       HostCSR& out) {
   if (!u || !v) return fail(SC_EINVAL, "edge arrays are NULL");
   if (n < 2 || m < 1) return fail(SC_EINVAL, "need n >= 2 and m >= 1");
   if (n >= (1ll << 31) || 2 * m >= (1ll << 31))
@@ -228,18 +226,34 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
     inv_f[x] = 1.0f / static_cast<float>(deg[x]);
     inv_d[x] = 1.0 / static_cast<double>(deg[x]);
   }
+  out.n = N;
+  out.m = m;
+  out.nslots = S;
+  out.rowptr = std::move(rowptr);
+  out.col = std::move(col);
+  out.deg = std::move(deg);
+  out.slot_row = std::move(slot_row);
+  out.slot_half = std::move(slot_half);
+  out.half_slot = std::move(half_slot);
+  out.tasks = std::move(tasks);
+  out.ptasks = std::move(ptasks);
+  out.wg_tasks = std::move(wg_tasks);
+  out.giant = std::move(giant);
+  out.nparts = nparts;
+  out.inv_f = std::move(inv_f);
+  out.inv_d = std::move(inv_d);
+  return SC_OK;
+}
 
-  sc_graph* g = new (std::nothrow) sc_graph();
-  if (!g) return fail(SC_ENOMEM, "host allocation failed");
-  (void)hipGetDevice(&g->device);
-  g->d.n = N;
-  g->d.m = m;
-  g->d.nslots = S;
-  g->d.ntasks = static_cast<int32_t>(tasks.size());
-  g->d.nptasks = static_cast<int32_t>(ptasks.size());
-  g->d.nwg = static_cast<int32_t>(wg_tasks.size());
-  g->d.ngiant = static_cast<int32_t>(giant.size());
-  g->d.nparts = nparts;
+int sc::upload_csr(const HostCSR& h, DeviceGraph& d) {
+  d.n = h.n;
+  d.m = h.m;
+  d.nslots = h.nslots;
+  d.ntasks = static_cast<int32_t>(h.tasks.size());
+  d.nptasks = static_cast<int32_t>(h.ptasks.size());
+  d.nwg = static_cast<int32_t>(h.wg_tasks.size());
+  d.ngiant = static_cast<int32_t>(h.giant.size());
+  d.nparts = h.nparts;
   auto up = [&](auto** dst, const auto& src) -> hipError_t {
     hipError_t e = dev_alloc(dst, src.size());
     if (e != hipSuccess) return e;
@@ -247,26 +261,42 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
     return hipMemcpy(*dst, src.data(), src.size() * sizeof(src[0]), hipMemcpyHostToDevice);
   };
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = up(&g->d.rowptr, rowptr);
-  if (e == hipSuccess) e = up(&g->d.col, col);
-  if (e == hipSuccess) e = up(&g->d.deg, deg);
-  if (e == hipSuccess) e = up(&g->d.slot_row, slot_row);
-  if (e == hipSuccess) e = up(&g->d.slot_half, slot_half);
-  if (e == hipSuccess) e = up(&g->d.half_slot, half_slot);
-  if (e == hipSuccess) e = up(&g->d.inv_deg_f, inv_f);
-  if (e == hipSuccess) e = up(&g->d.inv_deg_d, inv_d);
-  if (e == hipSuccess) e = up(&g->d.tasks, tasks);
-  if (e == hipSuccess) e = up(&g->d.wg_tasks, wg_tasks);
-  if (e == hipSuccess) e = up(&g->d.ptasks, ptasks);
-  if (e == hipSuccess) e = up(&g->d.giant, giant);
-  if (e != hipSuccess) {
-    g->release();
-    delete g;
+  if (e == hipSuccess) e = up(&d.rowptr, h.rowptr);
+  if (e == hipSuccess) e = up(&d.col, h.col);
+  if (e == hipSuccess) e = up(&d.deg, h.deg);
+  if (e == hipSuccess) e = up(&d.slot_row, h.slot_row);
+  if (e == hipSuccess) e = up(&d.slot_half, h.slot_half);
+  if (e == hipSuccess) e = up(&d.half_slot, h.half_slot);
+  if (e == hipSuccess) e = up(&d.inv_deg_f, h.inv_f);
+  if (e == hipSuccess) e = up(&d.inv_deg_d, h.inv_d);
+  if (e == hipSuccess) e = up(&d.tasks, h.tasks);
+  if (e == hipSuccess) e = up(&d.wg_tasks, h.wg_tasks);
+  if (e == hipSuccess) e = up(&d.ptasks, h.ptasks);
+  if (e == hipSuccess) e = up(&d.giant, h.giant);
+  if (e != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
                 std::string("graph upload: ") + hipGetErrorString(e));
+  return SC_OK;
+}
+
+extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                              unsigned flags, sc_graph** out) {
+  if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  sc::HostCSR h;
+  int rc = sc::build_host_csr(n, m, u, v, flags, h);
+  if (rc) return rc;
+  sc_graph* g = new (std::nothrow) sc_graph();
+  if (!g) return fail(SC_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&g->device);
+  rc = sc::upload_csr(h, g->d);
+  if (rc) {
+    g->release();
+    delete g;
+    return rc;
   }
-  g->rowptr_h = std::move(rowptr);
-  g->deg_h = std::move(deg);
+  g->rowptr_h = std::move(h.rowptr);
+  g->deg_h = std::move(h.deg);
   *out = g;
   return SC_OK;
 }
@@ -373,8 +403,13 @@ double ritz_bound(const std::vector<double>& alpha, const std::vector<double>& b
 }  // namespace
 
 int sc::compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
+  return lanczos_lambda_star(g->d, g->deg_h.data(), st, out);
+}
+
+int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipStream_t st,
+                            double* out) {
   using namespace sc;
-  const int64_t n = g->d.n;
+  const int64_t n = dg.n;
   const int kmax = static_cast<int>(std::min<int64_t>(n - 1, 160));
   const int64_t ld = n;
   double *V = nullptr, *w = nullptr, *h = nullptr, *sid = nullptr;
@@ -394,10 +429,10 @@ int sc::compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
   }
   // column 0: the top eigenvector sqrt(d)/sqrt(2m) (eigenvalue 1), deflated throughout
   std::vector<double> hv(n), sidh(n);
-  const double two_m = static_cast<double>(g->d.nslots);
+  const double two_m = static_cast<double>(dg.nslots);
   for (int64_t x = 0; x < n; ++x) {
-    hv[x] = std::sqrt(g->deg_h[x] / two_m);
-    sidh[x] = 1.0 / std::sqrt(static_cast<double>(g->deg_h[x]));
+    hv[x] = std::sqrt(deg_host[x] / two_m);
+    sidh[x] = 1.0 / std::sqrt(static_cast<double>(deg_host[x]));
   }
   // start vector: fixed pseudo-random, made orthogonal to column 0
   std::vector<double> v0(n);
@@ -428,7 +463,7 @@ int sc::compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
   const unsigned grid = static_cast<unsigned>((n + 255) / 256);
   for (int j = 1; j <= kmax; ++j) {
     const double* vj = V + static_cast<size_t>(j) * ld;
-    HIP_TRY(sc::launch_nmat_spmv(g->d, sid, vj, w, st));
+    HIP_TRY(sc::launch_nmat_spmv(dg, sid, vj, w, st));
     double a_j = 0.0;
     for (int pass = 0; pass < 2; ++pass) {   // full re-orthogonalisation, twice
       HIP_TRY(sc::launch_multi_dot(V, j + 1, ld, w, n, h, st));

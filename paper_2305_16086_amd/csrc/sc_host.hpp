@@ -97,6 +97,23 @@ struct sc_graph {
 
 namespace sc {
 
+// CSR and task lists of one graph, built and validated on the host.
+struct HostCSR {
+  int32_t n = 0;
+  int64_t m = 0, nslots = 0;
+  std::vector<int32_t> rowptr, col, deg, slot_row, slot_half, half_slot;
+  std::vector<Task> tasks, ptasks, wg_tasks;
+  std::vector<HeavyRow> giant;
+  int32_t nparts = 0;
+  std::vector<float> inv_f;
+  std::vector<double> inv_d;
+};
+
+int build_host_csr(int64_t n, int64_t m, const int64_t* u, const int64_t* v, unsigned flags,
+                   HostCSR& out);
+int upload_csr(const HostCSR& h, DeviceGraph& d);
+int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out);
+
 int ensure_buffers(sc_graph* g, int B, size_t tsize);
 int ensure_pipeline(sc_graph* g);
 int ensure_closure_buffers(sc_graph* g, size_t tsize);
