@@ -38,6 +38,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=48)
+    p.add_argument("--form", choices=["plain", "batch"], default="plain",
+                   help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
+                        "persistent launch against one graph at a time")
+    p.add_argument("--replay", action="store_true", help="batch: replay a captured hipGraph")
+    p.add_argument("--tune-json", default=None, help="batch: tuning table (written if absent)")
     return p.parse_args()
 
 
@@ -60,11 +65,165 @@ def cpu_baseline(graph, tau, tilde, nr, nsrc):
                       f"{m} edges", "host_cpus": os.cpu_count()}
 
 
+BATCH_EPS = 1e-2
+BATCH_MAX_L = 31
+LDS_PEAK_GBS = 128 * 256 * 2.4   # 128 B per clock per CU, 256 CUs, 2.4 GHz
+
+
+def batch_form(a):
+    """256 graphs (n uniform in [200, 20000]; G(n,p) deg 8, BA m=5, king grid)
+    by TGT at eps = 1e-2 with the automatic truncation capped at 31: one
+    persistent launch per step against the same graphs one at a time (TGT and
+    TGT+ through sc_all_edges_ex)."""
+    import tempfile
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+    from oracle import exact as ex
+
+    graphs = gg.workload("batch_256", 7)
+    M = sum(len(g[1]) for g in graphs)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    b = sc.sc_build_batch(graphs)
+    outs = [torch.empty(len(g[1]), dtype=torch.float64, device=dev) for g in graphs]
+
+    def opts(**kw):
+        return sc.sc_default_options(method=sc.SC_TGT, precision=0, max_L=BATCH_MAX_L,
+                                     stream=stream.cuda_stream, **kw)
+
+    path = a.tune_json or os.path.join(tempfile.gettempdir(), "sc_batch_tuning.json")
+    t0 = time.perf_counter()
+    sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(), out=outs)   # lambda* of every graph
+    torch.cuda.synchronize()
+    pre_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if os.path.exists(path):
+        sc.sc_batch_load_tuning(b, path)
+    else:
+        sc.sc_batch_autotune(b, BATCH_EPS, None, opts(), path)
+    tune_s = time.perf_counter() - t0
+    blocks = sc.sc_batch_blocks(b, opts())
+    flags = sc.SC_GRAPH_REPLAY if a.replay else 0
+    for _ in range(a.warmup):
+        sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(flags=flags), out=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(flags=flags), out=outs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    _, kst = sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(flags=sc.SC_TIME_KERNELS), out=outs)
+    res = [o.cpu().numpy() for o in outs]
+
+    # one graph at a time, same accuracy target
+    single = {}
+    taus = []
+    for name, method in (("tgt", sc.SC_TGT), ("tgt_plus", sc.SC_TGT_PLUS)):
+        vals = [torch.empty_like(o) for o in outs]
+        tau = [torch.empty(len(g[1]), dtype=torch.int32, device=dev) for g in graphs]
+        for i, g in enumerate(b.graphs):   # warm: per-graph buffers and plans
+            o = sc.sc_default_options(method=method, precision=0, max_L=BATCH_MAX_L,
+                                      stream=stream.cuda_stream)
+            sc.sc_all_edges_ex(g, BATCH_EPS, 0, o, out=vals[i], tau_out=tau[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, g in enumerate(b.graphs):
+            o = sc.sc_default_options(method=method, precision=0, max_L=BATCH_MAX_L,
+                                      stream=stream.cuda_stream)
+            sc.sc_all_edges_ex(g, BATCH_EPS, 0, o, out=vals[i])
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        single[name] = {"value": M / s, "ms": 1e3 * s,
+                        "vals": [x.cpu().numpy() for x in vals]}
+        if method == sc.SC_TGT:
+            taus = [t.cpu().numpy() for t in tau]
+    agree = max(float(np.abs(r - t).max()) for r, t in zip(res, single["tgt"]["vals"]))
+
+    # exact SC on the smallest graphs of each family
+    errs = {"batch": 0.0, "tgt": 0.0, "tgt_plus": 0.0}
+    checked = []
+    for fam in range(3):
+        idx = sorted([i for i in range(len(graphs)) if i % 3 == fam],
+                     key=lambda i: graphs[i][0])[:3]
+        for i in idx:
+            n, u, v = graphs[i]
+            exact = ex.sc_pinv(n, u, v)
+            errs["batch"] = max(errs["batch"], float(np.abs(res[i] - exact).max()))
+            for k in ("tgt", "tgt_plus"):
+                errs[k] = max(errs[k], float(np.abs(single[k]["vals"][i] - exact).max()))
+            checked.append(int(n))
+
+    # algorithmic bytes of the persistent launches: per item and step l = 2..tmax,
+    # neighbour values read (2m B) and rows written (n B), FP32
+    alg = 0.0
+    for i, (n, u, v) in enumerate(graphs):
+        tr = np.zeros(n, np.int64)
+        np.maximum.at(tr, u, taus[i])
+        np.maximum.at(tr, v, taus[i])
+        B = int(blocks[i])
+        nblk = (n + B - 1) // B
+        tb = np.zeros(nblk * B, np.int64)
+        tb[:n] = tr
+        tmax = tb.reshape(nblk, B).max(axis=1)
+        steps = np.maximum(tmax - 1, 0).sum()
+        alg += steps * (2 * len(u) + n) * B * 4.0
+    kms = kst["prop_ms"]
+    achieved = alg / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    hist = {int(k): int(c) for k, c in zip(*np.unique(blocks, return_counts=True))}
+    line = {
+        "metric": METRIC,
+        "value": M / dt,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch_256: 256 graphs, n uniform in [200, 20000], G(n,p) deg 8 / "
+                        f"BA m=5 / king grid (seed 7), sum n={sum(g[0] for g in graphs)}, "
+                        f"sum m={M}; TGT, eps=1e-2, lambda* truncation capped at "
+                        f"{BATCH_MAX_L}, FP32 propagation, FP64 sums",
+            "replay": bool(a.replay),
+            "blocks": hist,
+            "one_at_a_time_tgt_edges_per_s": single["tgt"]["value"],
+            "one_at_a_time_tgt_plus_edges_per_s": single["tgt_plus"]["value"],
+            "max_abs_diff_vs_one_at_a_time_tgt": agree,
+            "max_abs_err_exact": errs,
+            "exact_checked_n": checked,
+            "L_used": kst["L_used"], "L_min": kst["L_min"],
+            "preprocess_s": pre_s, "tune_s": tune_s,
+        },
+        "roofline": {
+            "bound": "lds",
+            "kernel": "k_batch (persistent, block states in LDS)",
+            "achieved": achieved,
+            "peak": LDS_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / LDS_PEAK_GBS,
+            "traffic": None,
+            "kernel_ms": kms,
+            "alg_bytes": alg,
+        },
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if a.form == "batch":
+        batch_form(a)
+        return
     import torch
     from paper_2305_16086_amd import sc
     import graphgen as gg

@@ -16,6 +16,7 @@ from .graphs import (  # noqa: F401
     gnp_connected,
     barabasi_albert,
     king_grid,
+    mixed_batch,
     rmat_lcc,
     random_small_connected,
     canonical_edges,

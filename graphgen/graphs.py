@@ -283,6 +283,26 @@ def rmat_lcc(scale: int, edge_factor: int, abcd=(0.57, 0.19, 0.19, 0.05), seed: 
 
 # ---------------------------------------------------------------- named workloads
 
+def mixed_batch(count: int, n_lo: int, n_hi: int, seed: int):
+    """Many graphs of uneven size: n_k uniform in [n_lo, n_hi], family k mod 3 =
+    G(n,p) with average degree 8 (components linked to the giant), Barabasi-Albert
+    with 5 edges per new node, king grid.  Per-graph seeds come from the master seed."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(n_lo, n_hi + 1, size=count)
+    seeds = rng.integers(1, 2**31 - 1, size=count)
+    out = []
+    for k in range(count):
+        n = int(sizes[k])
+        fam = k % 3
+        if fam == 0:
+            out.append(gnp_connected(n, 8.0, int(seeds[k])))
+        elif fam == 1:
+            out.append(barabasi_albert(n, 5, int(seeds[k])))
+        else:
+            out.append(king_grid(n))
+    return out
+
+
 def workload(name: str, seed: int = 1):
     """The evaluation workloads, by name.
 
@@ -290,6 +310,8 @@ def workload(name: str, seed: int = 1):
     * ``ba_100k``      : Barabasi-Albert, n=100,000, 10 edges per new node.
     * ``ba_small``     : Barabasi-Albert, n=2,000, 10 edges per new node (parity size).
     * ``rmat_s22``     : R-MAT scale 22, edge factor 16, LCC.
+    * ``batch_256``    : 256 graphs, n uniform in [200, 20,000], G(n,p) deg 8 /
+                         BA m = 5 / king grid in turn (a list of graphs).
     """
     if name == "tree_gnp_1k":
         return tree_plus_gnp(1000, 10.0, seed)
@@ -297,6 +319,8 @@ def workload(name: str, seed: int = 1):
         return barabasi_albert(100_000, 10, seed)
     if name == "ba_small":
         return barabasi_albert(2_000, 10, seed)
+    if name == "batch_256":
+        return mixed_batch(256, 200, 20_000, seed)
     if name == "rmat_s22":
         return rmat_lcc(22, 16, seed=seed)
     raise KeyError(name)

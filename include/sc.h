@@ -54,6 +54,8 @@ enum {
 /* run flags (sc_options.flags) */
 #define SC_DEVICE_PTRS 0x1u  /* out / trace arrays are device pointers */
 #define SC_TIME_KERNELS 0x4u /* bracket every propagation launch with HIP events (stats) */
+#define SC_GRAPH_REPLAY 0x8u /* sc_batch_all_edges: record the device work as a hipGraph
+                                on the first call, replay it on later identical calls */
 
 /* methods (sc_options.method) */
 #define SC_TGT 0       /* Algorithm 2: traversal to tau for every source */
@@ -219,6 +221,74 @@ int sc_mlp_grad(sc_mlp* net, const float* X, const float* z, const float* w, int
 /* y = network(X) for N samples, BF16 MFMA (bf16 = 1) or FP32 (bf16 = 0). */
 int sc_mlp_predict(const sc_mlp* net, const float* X, int64_t N, int bf16, float* y,
                    void* stream);
+
+/* ------------------------------------------------------------------ batches
+ *
+ * Not in the paper: many independent graphs through TGT (Algorithm 2) in one
+ * persistent launch.  Every graph's result is what sc_all_edges_ex gives for
+ * it with method SC_TGT and the same eps, L, precision and (for B in
+ * {16, 32, 64}) block: tau per edge from Theorem 3.2 with that graph's own
+ * lambda* (Eq. 6 with Upsilon = Delta = 0, capped at max_L) or a fixed odd L,
+ * and s(i,j) = g(i,j) + g(j,i) with the per-half-edge sums of Eq. 9.
+ * A work item is one source block of one graph; a workgroup runs all of its
+ * steps with the block's state in LDS when it fits (else in a device slab),
+ * taking items from an atomic ticket counter, longest first.
+ */
+typedef struct sc_batch sc_batch;
+
+/* Build G graph handles at once (each validated as by sc_build_graph; the
+ * error text names the failing graph) plus the sliced neighbour lists the
+ * batch kernel reads.  n[g], m[g]: sizes; u_host[g], v_host[g]: the m[g]
+ * edge endpoints of graph g (int64, host, copied).  flags as sc_build_graph. */
+int sc_build_batch(int G, const int64_t* n, const int64_t* m, const int64_t* const* u_host,
+                   const int64_t* const* v_host, unsigned flags, sc_batch** out);
+
+/* Number of graphs. */
+int sc_batch_size(const sc_batch* b, int* G);
+
+/* Graph i of the batch as an ordinary handle (borrowed: owned and freed by
+ * the batch; usable with every sc_graph call). */
+int sc_batch_graph(sc_batch* b, int i, sc_graph** g);
+
+/* Release the batch, its graphs and all device memory.  NULL is allowed. */
+void sc_free_batch(sc_batch* b);
+
+/*
+ * All-edge SC of every graph.  L: NULL (all automatic) or G ints, L[g] as
+ * the L argument of sc_all_edges (0 automatic, > 0 fixed odd-rounded).
+ * o: method must be SC_TGT; precision, max_L, lambda_star (applied to every
+ * graph when > 0), stream and flags as for sc_all_edges_ex; block: 0 = the
+ * tuned width of the graph's size bucket (sc_batch_autotune /
+ * sc_batch_load_tuning), else a built-in choice; or 1, 2, 4, 8, 16, 32, 64
+ * for every graph.  SC_GRAPH_REPLAY records the device work (truncation,
+ * initial terms, the persistent launches, the per-graph combination and,
+ * for host outputs, the copy to pinned staging) as a hipGraph and replays it
+ * while the arguments (and output pointers) stay the same.
+ * out: G pointers; out[g] receives m[g] doubles in graph g's input edge
+ * order (host memory, or device memory with SC_DEVICE_PTRS).
+ * st (may be NULL): L_used / L_min over all graphs, block (-1 when mixed),
+ * largest lambda*, prop_launches = persistent launches, prop_ms = their time
+ * (SC_TIME_KERNELS, not with SC_GRAPH_REPLAY), total_ms.
+ */
+int sc_batch_all_edges(sc_batch* b, double eps, const int32_t* L, const sc_options* o,
+                       double* const* out, sc_stats* st);
+
+/* The block width every graph would use under o (host int[G]). */
+int sc_batch_blocks(const sc_batch* b, const sc_options* o, int32_t* blocks_host);
+
+/*
+ * Measure the persistent launch for each size bucket (floor(log2 n),
+ * floor(log2 2m/n)) of the batch, on up to 8 of its largest graphs, for
+ * every B in {1, ..., 64} whose state fits the LDS (B <= 8 in device slabs
+ * otherwise); keep the fastest per bucket for o->precision and write the
+ * table with all timings as JSON to json_path (NULL: keep it in the handle
+ * only).  The computed values do not depend on the choice beyond rounding.
+ */
+int sc_batch_autotune(sc_batch* b, double eps, const int32_t* L, const sc_options* o,
+                      const char* json_path);
+
+/* Load a table written by sc_batch_autotune (replaces the handle's table). */
+int sc_batch_load_tuning(sc_batch* b, const char* json_path);
 
 /* Text for an error code; never NULL. */
 const char* sc_strerror(int code);

@@ -279,17 +279,11 @@ int sc::upload_csr(const HostCSR& h, DeviceGraph& d) {
   return SC_OK;
 }
 
-extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
-                              unsigned flags, sc_graph** out) {
-  if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
-  *out = nullptr;
-  sc::HostCSR h;
-  int rc = sc::build_host_csr(n, m, u, v, flags, h);
-  if (rc) return rc;
+int sc::graph_from_csr(HostCSR& h, sc_graph** out) {
   sc_graph* g = new (std::nothrow) sc_graph();
   if (!g) return fail(SC_ENOMEM, "host allocation failed");
   (void)hipGetDevice(&g->device);
-  rc = sc::upload_csr(h, g->d);
+  const int rc = sc::upload_csr(h, g->d);
   if (rc) {
     g->release();
     delete g;
@@ -299,6 +293,16 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   g->deg_h = std::move(h.deg);
   *out = g;
   return SC_OK;
+}
+
+extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                              unsigned flags, sc_graph** out) {
+  if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  sc::HostCSR h;
+  const int rc = sc::build_host_csr(n, m, u, v, flags, h);
+  if (rc) return rc;
+  return sc::graph_from_csr(h, out);
 }
 
 extern "C" int sc_graph_size(const sc_graph* g, int64_t* n, int64_t* m) {

@@ -112,6 +112,8 @@ struct HostCSR {
 int build_host_csr(int64_t n, int64_t m, const int64_t* u, const int64_t* v, unsigned flags,
                    HostCSR& out);
 int upload_csr(const HostCSR& h, DeviceGraph& d);
+// New handle owning an upload of h (h.rowptr and h.deg are moved into it).
+int graph_from_csr(HostCSR& h, sc_graph** out);
 int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out);
 
 int ensure_buffers(sc_graph* g, int B, size_t tsize);

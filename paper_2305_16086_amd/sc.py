@@ -28,6 +28,7 @@ SC_ENOTIMPL = -8
 SC_MERGE_DUPS = 0x2
 SC_DEVICE_PTRS = 0x1
 SC_TIME_KERNELS = 0x4
+SC_GRAPH_REPLAY = 0x8
 
 SC_TGT = 0
 SC_TGT_PLUS = 1
@@ -144,6 +145,25 @@ def _load():
     lib.sc_mlp_predict.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
                                    C.c_void_p]
     lib.sc_mlp_predict.restype = C.c_int
+    lib.sc_build_batch.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint, C.POINTER(C.c_void_p)]
+    lib.sc_build_batch.restype = C.c_int
+    lib.sc_batch_size.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.sc_batch_size.restype = C.c_int
+    lib.sc_batch_graph.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]
+    lib.sc_batch_graph.restype = C.c_int
+    lib.sc_free_batch.argtypes = [C.c_void_p]
+    lib.sc_free_batch.restype = None
+    lib.sc_batch_all_edges.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.POINTER(ScOptions),
+                                       C.c_void_p, C.POINTER(ScStats)]
+    lib.sc_batch_all_edges.restype = C.c_int
+    lib.sc_batch_blocks.argtypes = [C.c_void_p, C.POINTER(ScOptions), C.c_void_p]
+    lib.sc_batch_blocks.restype = C.c_int
+    lib.sc_batch_autotune.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.POINTER(ScOptions),
+                                      C.c_char_p]
+    lib.sc_batch_autotune.restype = C.c_int
+    lib.sc_batch_load_tuning.argtypes = [C.c_void_p, C.c_char_p]
+    lib.sc_batch_load_tuning.restype = C.c_int
     return lib
 
 
@@ -154,7 +174,9 @@ EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_gr
             "sc_lambda_star", "sc_all_edges", "sc_all_edges_ex", "sc_strerror",
             "sc_last_error", "sc_version", "sc_default_train_options", "sc_mlp_create",
             "sc_mlp_free", "sc_mlp_get", "sc_mlp_set", "sc_closure_dataset",
-            "sc_closure_features", "sc_mlp_train", "sc_mlp_grad", "sc_mlp_predict"]
+            "sc_closure_features", "sc_mlp_train", "sc_mlp_grad", "sc_mlp_predict",
+            "sc_build_batch", "sc_batch_size", "sc_batch_graph", "sc_free_batch",
+            "sc_batch_all_edges", "sc_batch_blocks", "sc_batch_autotune", "sc_batch_load_tuning"]
 
 
 def _check(rc, where):
@@ -427,3 +449,118 @@ def sc_mlp_predict(net: Mlp, X, bf16: int = 1, y=None):
     _check(_lib.sc_mlp_predict(net.handle, _dev(X, torch.float32, 16 * N, "X"), N, int(bf16),
                                _dev(y, torch.float32, N, "y"), _stream_of(X)), "sc_mlp_predict")
     return y
+
+
+# ---------------------------------------------------------------- batches
+
+class Batch:
+    """Owning wrapper of an sc_batch handle; ``graphs[i]`` are borrowed handles."""
+
+    def __init__(self, handle, sizes):
+        self._h = handle
+        self.sizes = sizes          # [(n, m)] per graph
+        self.graphs = []
+        for i, (n, m) in enumerate(sizes):
+            gh = C.c_void_p()
+            _check(_lib.sc_batch_graph(handle, i, C.byref(gh)), "sc_batch_graph")
+            g = Graph(gh, n, m)
+            g.free = lambda: None       # owned by the batch
+            g._h = gh
+            self.graphs.append(g)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch already freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            for g in self.graphs:
+                g._h = None
+            _lib.sc_free_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sc_build_batch(graphs, flags: int = 0) -> Batch:
+    """graphs: list of (n, u, v)."""
+    G = len(graphs)
+    ns = np.array([int(g[0]) for g in graphs], dtype=np.int64)
+    us = [np.ascontiguousarray(g[1], dtype=np.int64) for g in graphs]
+    vs = [np.ascontiguousarray(g[2], dtype=np.int64) for g in graphs]
+    ms = np.array([len(u) for u in us], dtype=np.int64)
+    up = (C.c_void_p * G)(*[u.ctypes.data for u in us])
+    vp = (C.c_void_p * G)(*[v.ctypes.data for v in vs])
+    h = C.c_void_p()
+    rc = _lib.sc_build_batch(G, ns.ctypes.data, ms.ctypes.data, up, vp, int(flags), C.byref(h))
+    _check(rc, "sc_build_batch")
+    return Batch(h, [(int(ns[i]), int(ms[i])) for i in range(G)])
+
+
+def _L_array(b: Batch, L):
+    if L is None:
+        return None
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.int32), (len(b.sizes),)))
+    return L
+
+
+def sc_batch_all_edges(b: Batch, eps: float, L=None, options: ScOptions | None = None,
+                       out=None):
+    """out: None (host arrays are allocated), a list of numpy arrays, or a list
+    of CUDA float64 tensors (then SC_DEVICE_PTRS and the current torch stream).
+    Returns (list of outputs, stats dict)."""
+    o = options if options is not None else sc_default_options()
+    G = len(b.sizes)
+    if out is None:
+        out = [np.empty(m, dtype=np.float64) for _, m in b.sizes]
+    if len(out) != G:
+        raise ValueError("need one output per graph")
+    device = not isinstance(out[0], np.ndarray)
+    for x, (_, m) in zip(out, b.sizes):
+        if device:
+            import torch
+            if isinstance(x, np.ndarray) or x.dtype != torch.float64 or not x.is_cuda or x.numel() != m:
+                raise ValueError("device outputs must be CUDA float64 tensors of length m")
+        elif not isinstance(x, np.ndarray) or x.dtype != np.float64 or x.shape != (m,) \
+                or not x.flags.c_contiguous:
+            raise ValueError("host outputs must be contiguous float64 arrays of length m")
+    if device:
+        import torch
+        o.flags |= SC_DEVICE_PTRS
+        if not o.stream:
+            o.stream = torch.cuda.current_stream(out[0].device).cuda_stream
+    else:
+        o.flags &= ~SC_DEVICE_PTRS
+    ptrs = (C.c_void_p * G)(*[_ptr(x) for x in out])
+    La = _L_array(b, L)
+    st = ScStats()
+    rc = _lib.sc_batch_all_edges(b.handle, float(eps), None if La is None else La.ctypes.data,
+                                 C.byref(o), ptrs, C.byref(st))
+    _check(rc, "sc_batch_all_edges")
+    return out, st.as_dict()
+
+
+def sc_batch_blocks(b: Batch, options: ScOptions | None = None) -> np.ndarray:
+    o = options if options is not None else sc_default_options()
+    blocks = np.empty(len(b.sizes), dtype=np.int32)
+    _check(_lib.sc_batch_blocks(b.handle, C.byref(o), blocks.ctypes.data), "sc_batch_blocks")
+    return blocks
+
+
+def sc_batch_autotune(b: Batch, eps: float, L=None, options: ScOptions | None = None,
+                      json_path: str | None = None):
+    o = options if options is not None else sc_default_options()
+    La = _L_array(b, L)
+    rc = _lib.sc_batch_autotune(b.handle, float(eps), None if La is None else La.ctypes.data,
+                                C.byref(o), json_path.encode() if json_path else None)
+    _check(rc, "sc_batch_autotune")
+
+
+def sc_batch_load_tuning(b: Batch, json_path: str):
+    _check(_lib.sc_batch_load_tuning(b.handle, json_path.encode()), "sc_batch_load_tuning")
