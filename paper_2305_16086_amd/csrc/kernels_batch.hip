@@ -12,9 +12,10 @@
 //
 // Rows are read through a sliced layout: the rows of a graph sorted by degree
 // (descending) form groups of 64, and a group's neighbour lists are stored
-// column-major, nb[off + t * 64 + i] = t-th neighbour of the group's row i
-// (the zero row n past the row's degree), so one load instruction fetches
-// slot t of consecutive rows.  A lane owns (row, V consecutive columns) and
+// column-major in 32-bit words, word w of row i at nb[off + w * 64 + i]
+// holding slots K w .. K w + K - 1 (K = 2: 16-bit ids, for graphs below 65535
+// nodes; K = 1: 32-bit ids), so one load instruction fetches a word of 64
+// consecutive rows; lanes past their row's degree read the zero row n.  A lane owns (row, V consecutive columns) and
 // adds the row's neighbour values in the order the single-graph kernels use
 // for the same B (sequential for B = 64; G = 64 / B interleaved partial sums
 // combined as a butterfly for B = 16, 32; heavy rows in four interleaved
@@ -63,11 +64,19 @@ __device__ inline void tree(T (&acc)[G][V], T (&out)[V]) {
   for (int e = 0; e < V; ++e) out[e] = acc[0][e];
 }
 
+// Slot t of a lane's row: word t / K of its column of the group (K = 2: two
+// 16-bit ids per word, low half first).
+template <int K>
+__device__ inline int slot_index(const uint32_t* __restrict__ nw, int t) {
+  const uint32_t w = nw[(t / K) * 64];
+  return K == 1 ? static_cast<int>(w) : static_cast<int>((w >> (16 * (t & 1))) & 0xFFFFu);
+}
+
 // Neighbour slots [b, e) of one lane's row taken in the workgroup-task order:
 // four interleaved 64-slot pieces (piece p belongs to part p mod 4), each part
 // with G interleaved partial sums, parts added in order.
-template <typename T, int B, int V, int G>
-__device__ inline void chunk_sum(const int32_t* __restrict__ nb, const T* Y, int cv, int b, int e,
+template <typename T, int B, int V, int G, int K>
+__device__ inline void chunk_sum(const uint32_t* __restrict__ nw, const T* Y, int cv, int b, int e,
                                  T (&tot)[V]) {
 #pragma unroll 1
   for (int w = 0; w < kWavesPerBlock; ++w) {
@@ -83,7 +92,8 @@ __device__ inline void chunk_sum(const int32_t* __restrict__ nb, const T* Y, int
         for (int g = 0; g < G; ++g) {
           const int t = t0 + g;
           if (t < pe) {
-            const Pack<T, V> p = load_pack<T, V>(Y + static_cast<size_t>(nb[t * 64]) * B + cv);
+            const int u = slot_index<K>(nw, t);
+            const Pack<T, V> p = load_pack<T, V>(Y + static_cast<size_t>(u) * B + cv);
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[g][q] += p.v[q];
           }
@@ -97,8 +107,71 @@ __device__ inline void chunk_sum(const int32_t* __restrict__ nb, const T* Y, int
   }
 }
 
-// Propagation of one graph's block state: Yn = P Yp for all rows.
-template <typename T, int B, int NT>
+// Rows of more than kChunk neighbours (and lanes sharing their pass) in the
+// order of the single-graph workgroup tasks; giant rows chunk by chunk.
+template <typename T, int B, int V, int G, int K>
+__device__ inline void heavy_sum(const uint32_t* __restrict__ nw, const T* Yp, int cv, int d,
+                                 T (&out)[V]) {
+  if (d <= kChunk) {
+    T acc[G][V];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[gg][q] = T(0);
+    for (int t0 = 0; t0 < d; t0 += G) {
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) {
+        const int t = t0 + gg;
+        if (t < d) {
+          const Pack<T, V> pk = load_pack<T, V>(Yp + static_cast<size_t>(slot_index<K>(nw, t)) * B + cv);
+#pragma unroll
+          for (int q = 0; q < V; ++q) acc[gg][q] += pk.v[q];
+        }
+      }
+    }
+    tree<T, G, V>(acc, out);
+  } else if (d <= kGiant) {
+    chunk_sum<T, B, V, G, K>(nw, Yp, cv, 0, d, out);
+  } else {
+#pragma unroll
+    for (int q = 0; q < V; ++q) out[q] = T(0);
+    for (int b = 0; b < d; b += kGiantChunk) {
+      T c[V];
+      chunk_sum<T, B, V, G, K>(nw, Yp, cv, b, min(b + kGiantChunk, d), c);
+#pragma unroll
+      for (int q = 0; q < V; ++q) out[q] += c[q];
+    }
+  }
+}
+
+// Slots per gather batch; group widths are padded to a multiple of it.
+static_assert(kBatchSlots == 8, "gather_batch is written for 8 slots");
+
+// One batch of 8 slots (8 / K words): every slot inside the padded group width
+// holds a real neighbour or the zero row n, so no slot needs a mask; slot s
+// goes to partial sum s mod G (the single-graph order).
+template <typename T, int B, int V, int G, int K>
+__device__ inline void gather_batch(const uint32_t (&wd)[kBatchSlots / K], const T* Yp, int cv,
+                                    T (&acc)[G][V]) {
+  int u[kBatchSlots];
+#pragma unroll
+  for (int s = 0; s < kBatchSlots; ++s)
+    u[s] = K == 1 ? static_cast<int>(wd[s]) : static_cast<int>((wd[s / 2] >> (16 * (s & 1))) & 0xFFFFu);
+  Pack<T, V> pk[kBatchSlots];
+#pragma unroll
+  for (int s = 0; s < kBatchSlots; ++s) pk[s] = load_pack<T, V>(Yp + static_cast<size_t>(u[s]) * B + cv);
+#pragma unroll
+  for (int s = 0; s < kBatchSlots; ++s)
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[s % G][e] += pk[s].v[e];
+}
+
+// Propagation of one graph's block state: Yn = P Yp for all rows.  Each wave
+// walks its passes (group gi = wave, wave + NW, ...; LR passes per group) and
+// fetches the next pass's row descriptors and first neighbour words before
+// it gathers the current pass.  Rows are sorted by degree, so a pass's width
+// is the degree of its first row (lane 0).
+template <typename T, int B, int NT, int K>
 __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   constexpr int V = (B * sizeof(T) < 16) ? B : static_cast<int>(16 / sizeof(T));
   constexpr int LR = B / V;           // lanes per row
@@ -106,81 +179,65 @@ __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   constexpr int G = B >= 16 ? 64 / B : 1;
   constexpr bool kEmul = B >= 16;     // single-graph kernels exist for these widths
   constexpr int NW = NT / 64;
+  constexpr int kW = kBatchSlots / K; // words per batch
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = g.n;
   const T* __restrict__ inv = inv_of<T>(g);
+  const uint32_t* __restrict__ nbw = g.nb;
   const int cv = (lane % LR) * V;
-  for (int gi = wave; gi < g.ngroups; gi += NW) {
-    const int2 gd = g.grp[gi];
-#pragma unroll 1
-    for (int p = 0; p < LR; ++p) {
-      const int i = p * RPP + lane / LR;
-      const int2 rd = g.grp_rows[gi * 64 + i];
-      const int x = rd.x;
-      const int d = rd.y;
-      const int wmax = wave_max_i(d);
-      const int32_t* __restrict__ nb = g.nb + gd.x + i;
-      T out[V];
-      if (kEmul && wmax > kChunk) {
-        if (d <= kChunk) {
-          T acc[G][V];
+  const int nq = wave < g.ngroups ? ((g.ngroups - 1 - wave) / NW + 1) * LR : 0;
+  uint32_t wn[kW];
+  int2 rdn = make_int2(n, 0);
+  int offn = 0;
+  if (nq > 0) {
+    const int i = lane / LR;
+    offn = g.grp[wave].x + i;
+    rdn = g.grp_rows[wave * 64 + i];
 #pragma unroll
-          for (int gg = 0; gg < G; ++gg)
+    for (int w = 0; w < kW; ++w) wn[w] = nbw[offn + w * 64];
+  }
+  for (int q = 0; q < nq; ++q) {
+    uint32_t wc[kW];
 #pragma unroll
-            for (int q = 0; q < V; ++q) acc[gg][q] = T(0);
-          for (int t0 = 0; t0 < d; t0 += G) {
+    for (int w = 0; w < kW; ++w) wc[w] = wn[w];
+    const int x = rdn.x;
+    const int d = rdn.y;
+    const int off = offn;
+    if (q + 1 < nq) {
+      const int gi = wave + ((q + 1) / LR) * NW;
+      const int i = ((q + 1) % LR) * RPP + lane / LR;
+      offn = g.grp[gi].x + i;
+      rdn = g.grp_rows[gi * 64 + i];
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-              const int t = t0 + gg;
-              if (t < d) {
-                const Pack<T, V> pk = load_pack<T, V>(Yp + static_cast<size_t>(nb[t * 64]) * B + cv);
+      for (int w = 0; w < kW; ++w) wn[w] = nbw[offn + w * 64];
+    }
+    const int wmax = __builtin_amdgcn_readfirstlane(d);
+    const uint32_t* __restrict__ nw = nbw + off;
+    T out[V];
+    if (kEmul && wmax > kChunk) {
+      heavy_sum<T, B, V, G, K>(nw, Yp, cv, d, out);
+    } else {
+      T acc[G][V];
 #pragma unroll
-                for (int q = 0; q < V; ++q) acc[gg][q] += pk.v[q];
-              }
-            }
-          }
-          tree<T, G, V>(acc, out);
-        } else if (d <= kGiant) {
-          chunk_sum<T, B, V, G>(nb, Yp, cv, 0, d, out);
-        } else {
+      for (int gg = 0; gg < G; ++gg)
 #pragma unroll
-          for (int q = 0; q < V; ++q) out[q] = T(0);
-          for (int b = 0; b < d; b += kGiantChunk) {
-            T c[V];
-            chunk_sum<T, B, V, G>(nb, Yp, cv, b, min(b + kGiantChunk, d), c);
+        for (int e = 0; e < V; ++e) acc[gg][e] = T(0);
+      gather_batch<T, B, V, G, K>(wc, Yp, cv, acc);
+      for (int t0 = kBatchSlots; t0 < wmax; t0 += kBatchSlots) {
+        uint32_t wd[kW];
 #pragma unroll
-            for (int q = 0; q < V; ++q) out[q] += c[q];
-          }
-        }
-      } else {
-        // light rows: slot t goes to partial sum t mod G; padding reads the zero row
-        constexpr int kU = 8;
-        T acc[G][V];
-#pragma unroll
-        for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-          for (int q = 0; q < V; ++q) acc[gg][q] = T(0);
-        for (int t0 = 0; t0 < wmax; t0 += kU) {
-          int u[kU];
-#pragma unroll
-          for (int q = 0; q < kU; ++q) u[q] = (t0 + q < wmax) ? nb[(t0 + q) * 64] : n;
-#pragma unroll
-          for (int q = 0; q < kU; ++q) {
-            const Pack<T, V> pk = load_pack<T, V>(Yp + static_cast<size_t>(u[q]) * B + cv);
-#pragma unroll
-            for (int e = 0; e < V; ++e) acc[q % G][e] += pk.v[e];
-          }
-        }
-        tree<T, G, V>(acc, out);
+        for (int w = 0; w < kW; ++w) wd[w] = nw[(t0 / K + w) * 64];
+        gather_batch<T, B, V, G, K>(wd, Yp, cv, acc);
       }
-      if (x < n) {
-        const T s = inv[x];
-        Pack<T, V> o;
+      tree<T, G, V>(acc, out);
+    }
+    if (x < n) {
+      const T s = inv[x];
+      Pack<T, V> o;
 #pragma unroll
-        for (int q = 0; q < V; ++q) o.v[q] = out[q] * s;
-        *reinterpret_cast<Pack<T, V>*>(Yn + static_cast<size_t>(x) * B + cv) = o;
-      }
+      for (int e = 0; e < V; ++e) o.v[e] = out[e] * s;
+      *reinterpret_cast<Pack<T, V>*>(Yn + static_cast<size_t>(x) * B + cv) = o;
     }
   }
 }
@@ -188,8 +245,8 @@ __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
 constexpr int kAccRegs = 2;   // accumulation slots kept in registers per thread
 
 // One item: block [s0, s0 + B) of graph g, all steps.
-template <typename T, int B, int NT>
-__device__ void run_item(const BatchGraph& g, int s0, T* Y0, T* Y1, int* s_tmax) {
+template <typename T, int B, int NT, int K>
+__device__ __forceinline__ void run_item(const BatchGraph& g, int s0, T* Y0, T* Y1, int* s_tmax) {
   const int tid = threadIdx.x;
   const int n = g.n;
   const int ncols = min(B, n - s0);
@@ -236,7 +293,7 @@ __device__ void run_item(const BatchGraph& g, int s0, T* Y0, T* Y1, int* s_tmax)
   T* Yp = Y0;
   T* Yn = Y1;
   for (int ell = 2; ell <= tmax; ++ell) {
-    rows_step<T, B, NT>(g, Yp, Yn);
+    rows_step<T, B, NT, K>(g, Yp, Yn);
     __syncthreads();
     // gacc[k] += (p_l(s,s) - p_l(j,s)) / d_s for l <= tau_k (Eq. 9)
 #pragma unroll
@@ -266,7 +323,7 @@ __device__ void run_item(const BatchGraph& g, int s0, T* Y0, T* Y1, int* s_tmax)
     if (rt[r] >= 0) g.gacc[kbeg + tid + r * NT] = racc[r];
 }
 
-template <typename T, int NT, bool kLds>
+template <typename T, int NT, bool kLds, int B>
 __global__ __launch_bounds__(NT) void k_batch(const BatchGraph* __restrict__ graphs,
                                               const BatchItem* __restrict__ items, int nitems,
                                               int* __restrict__ ticket, T* __restrict__ slabs,
@@ -283,16 +340,11 @@ __global__ __launch_bounds__(NT) void k_batch(const BatchGraph* __restrict__ gra
     const BatchItem w = items[it];
     const BatchGraph g = graphs[w.graph];
     T* Y0 = kLds ? reinterpret_cast<T*>(smem) : slabs + static_cast<int64_t>(blockIdx.x) * slab_elems;
-    T* Y1 = Y0 + static_cast<int64_t>(g.n + 1) * g.B;
-    switch (g.B) {
-      case 1: run_item<T, 1, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      case 2: run_item<T, 2, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      case 4: run_item<T, 4, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      case 8: run_item<T, 8, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      case 16: run_item<T, 16, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      case 32: run_item<T, 32, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-      default: run_item<T, 64, NT>(g, w.s0, Y0, Y1, &s_tmax); break;
-    }
+    T* Y1 = Y0 + static_cast<int64_t>(g.n + 1) * B;
+    if (g.narrow)
+      run_item<T, B, NT, 2>(g, w.s0, Y0, Y1, &s_tmax);
+    else
+      run_item<T, B, NT, 1>(g, w.s0, Y0, Y1, &s_tmax);
   }
 }
 
@@ -309,47 +361,75 @@ __global__ void k_tau_range(const int32_t* __restrict__ tau_row, int64_t count, 
   atomicMax(&mm[1], tau_row[i]);
 }
 
-template <typename T, int NT, bool kLds>
+template <typename T, int NT, bool kLds, int B>
 const void* batch_kernel() {
-  return reinterpret_cast<const void*>(&k_batch<T, NT, kLds>);
+  return reinterpret_cast<const void*>(&k_batch<T, NT, kLds, B>);
+}
+
+template <typename T, int NT, bool kLds>
+const void* batch_kernel_b(int B) {
+  switch (B) {
+    case 1: return batch_kernel<T, NT, kLds, 1>();
+    case 2: return batch_kernel<T, NT, kLds, 2>();
+    case 4: return batch_kernel<T, NT, kLds, 4>();
+    case 8: return batch_kernel<T, NT, kLds, 8>();
+    case 16: return batch_kernel<T, NT, kLds, 16>();
+    case 32: return batch_kernel<T, NT, kLds, 32>();
+    case 64: return batch_kernel<T, NT, kLds, 64>();
+    default: return nullptr;
+  }
+}
+
+template <typename T, int NT, bool kLds, int B>
+void launch_one(int grid, size_t dyn, const BatchGraph* graphs, const BatchItem* items, int nitems,
+                int* ticket, T* slabs, int64_t slab_elems, hipStream_t st) {
+  k_batch<T, NT, kLds, B><<<grid, NT, dyn, st>>>(graphs, items, nitems, ticket, slabs, slab_elems);
+}
+
+template <typename T, int NT, bool kLds>
+hipError_t launch_b(int B, int grid, size_t dyn, const BatchGraph* graphs, const BatchItem* items,
+                    int nitems, int* ticket, T* slabs, int64_t slab_elems, hipStream_t st) {
+  switch (B) {
+    case 1: launch_one<T, NT, kLds, 1>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 2: launch_one<T, NT, kLds, 2>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 4: launch_one<T, NT, kLds, 4>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 8: launch_one<T, NT, kLds, 8>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 16: launch_one<T, NT, kLds, 16>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 32: launch_one<T, NT, kLds, 32>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    case 64: launch_one<T, NT, kLds, 64>(grid, dyn, graphs, items, nitems, ticket, slabs, slab_elems, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 template <typename T>
-const void* batch_kernel_ptr(int nt, bool lds) {
-  if (!lds) return batch_kernel<T, 256, false>();   // slab states: 256-thread workgroups
+const void* batch_kernel_ptr(int nt, bool lds, int B) {
+  if (!lds) return batch_kernel_b<T, 256, false>(B);   // slab states: 256-thread workgroups
   switch (nt) {
-    case 256: return batch_kernel<T, 256, true>();
-    case 512: return batch_kernel<T, 512, true>();
-    case 1024: return batch_kernel<T, 1024, true>();
+    case 256: return batch_kernel_b<T, 256, true>(B);
+    case 512: return batch_kernel_b<T, 512, true>(B);
+    case 1024: return batch_kernel_b<T, 1024, true>(B);
     default: return nullptr;
   }
 }
 
 template <typename T>
-hipError_t launch_batch(int nt, bool lds, int grid, size_t dyn_lds, const BatchGraph* graphs,
+hipError_t launch_batch(int nt, bool lds, int B, int grid, size_t dyn_lds, const BatchGraph* graphs,
                         const BatchItem* items, int nitems, int* ticket, T* slabs,
                         int64_t slab_elems, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (!lds) {
     if (nt != 256) return hipErrorInvalidValue;
-    k_batch<T, 256, false><<<grid, 256, 0, st>>>(graphs, items, nitems, ticket, slabs, slab_elems);
-    return hipGetLastError();
+    return launch_b<T, 256, false>(B, grid, 0, graphs, items, nitems, ticket, slabs, slab_elems, st);
   }
   switch (nt) {
-    case 256:
-      k_batch<T, 256, true><<<grid, 256, dyn_lds, st>>>(graphs, items, nitems, ticket, slabs, slab_elems);
-      break;
-    case 512:
-      k_batch<T, 512, true><<<grid, 512, dyn_lds, st>>>(graphs, items, nitems, ticket, slabs, slab_elems);
-      break;
-    case 1024:
-      k_batch<T, 1024, true><<<grid, 1024, dyn_lds, st>>>(graphs, items, nitems, ticket, slabs, slab_elems);
-      break;
+    case 256: return launch_b<T, 256, true>(B, grid, dyn_lds, graphs, items, nitems, ticket, slabs, slab_elems, st);
+    case 512: return launch_b<T, 512, true>(B, grid, dyn_lds, graphs, items, nitems, ticket, slabs, slab_elems, st);
+    case 1024: return launch_b<T, 1024, true>(B, grid, dyn_lds, graphs, items, nitems, ticket, slabs, slab_elems, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st) {
@@ -364,12 +444,12 @@ hipError_t launch_tau_range(const int32_t* tau_row, int64_t count, int32_t* mm, 
   return hipGetLastError();
 }
 
-template const void* batch_kernel_ptr<float>(int, bool);
-template const void* batch_kernel_ptr<double>(int, bool);
-template hipError_t launch_batch<float>(int, bool, int, size_t, const BatchGraph*,
+template const void* batch_kernel_ptr<float>(int, bool, int);
+template const void* batch_kernel_ptr<double>(int, bool, int);
+template hipError_t launch_batch<float>(int, bool, int, int, size_t, const BatchGraph*,
                                         const BatchItem*, int, int*, float*, int64_t,
                                         hipStream_t);
-template hipError_t launch_batch<double>(int, bool, int, size_t, const BatchGraph*,
+template hipError_t launch_batch<double>(int, bool, int, int, size_t, const BatchGraph*,
                                          const BatchItem*, int, int*, double*, int64_t,
                                          hipStream_t);
 

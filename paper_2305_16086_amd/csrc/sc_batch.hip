@@ -19,6 +19,7 @@ using sc::fail;
 namespace {
 
 constexpr int kClasses = 4;         // LDS <= budget/4, <= budget/2, <= budget, device slab
+constexpr int kLaunchMax = kClasses * 7;   // one persistent launch per (class, block width)
 constexpr int kClassThreads[kClasses] = {256, 512, 1024, 256};
 constexpr size_t kStaticLds = 64;   // the kernel's own __shared__ words (rounded up)
 constexpr size_t kSlabCap = size_t(8) << 30;   // device memory for slab states
@@ -37,7 +38,8 @@ struct sc_batch {
   std::vector<int64_t> node_off, slot_off, edge_off;   // [G + 1]
   std::vector<int32_t> dmin;                           // smallest degree per graph
   // sliced neighbour lists (built once)
-  std::vector<int32_t*> nb;
+  std::vector<uint32_t*> nb;
+  std::vector<int32_t> narrow;
   std::vector<int2*> grp, grp_rows;
   std::vector<int32_t> ngroups;
   // run buffers (batch-wide, indexed by the offsets)
@@ -49,7 +51,7 @@ struct sc_batch {
   sc::BatchGraph* d_graphs = nullptr;
   sc::BatchItem* d_items = nullptr;
   size_t items_cap = 0;
-  int32_t* d_misc = nullptr;       // [0, kClasses): tickets; [kClasses, +2): tau min / max
+  int32_t* d_misc = nullptr;       // [0, kLaunchMax): tickets; [kLaunchMax, +2): tau min / max
   int32_t* h_misc = nullptr;       // pinned copy of the tau range
   void* slabs = nullptr;
   size_t slab_bytes = 0;
@@ -102,10 +104,13 @@ struct sc_batch {
 namespace {
 
 // Rows sorted by degree (descending, ties by id) in groups of 64 with their
-// neighbour lists column-major, padded with the zero row n.
-int build_slices(const sc::HostCSR& h, std::vector<int32_t>& nb, std::vector<int2>& grp,
-                 std::vector<int2>& grp_rows) {
+// neighbour lists column-major in 32-bit words (two 16-bit ids per word when
+// n < 65535), padded with the zero row n, plus kBatchWordPad words at the end.
+int build_slices(const sc::HostCSR& h, std::vector<uint32_t>& nb, std::vector<int2>& grp,
+                 std::vector<int2>& grp_rows, int* narrow) {
   const int n = h.n;
+  const int K = n < 65535 ? 2 : 1;
+  *narrow = K == 2 ? 1 : 0;
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
@@ -116,17 +121,29 @@ int build_slices(const sc::HostCSR& h, std::vector<int32_t>& nb, std::vector<int
   int64_t off = 0;
   for (int gi = 0; gi < ngroups; ++gi) {
     const int width = h.deg[order[gi * 64]];
-    if (off > INT32_MAX - int64_t(width) * 64) return fail(SC_EINVAL, "batch graph too large");
+    const int64_t padded = (width + sc::kBatchSlots - 1) / sc::kBatchSlots * sc::kBatchSlots;
+    const int64_t words = padded / K;
+    if (off > INT32_MAX - words * 64 - sc::kBatchWordPad) return fail(SC_EINVAL, "batch graph too large");
     grp[gi] = make_int2(static_cast<int>(off), width);
-    off += int64_t(width) * 64;
+    off += words * 64;
   }
-  nb.assign(static_cast<size_t>(off), n);
+  const uint32_t pad_word = K == 2 ? (static_cast<uint32_t>(n) << 16) | static_cast<uint32_t>(n)
+                                   : static_cast<uint32_t>(n);
+  nb.assign(static_cast<size_t>(off) + sc::kBatchWordPad, pad_word);
   for (int gi = 0; gi < ngroups; ++gi) {
     for (int i = 0; i < 64 && gi * 64 + i < n; ++i) {
       const int x = order[gi * 64 + i];
       grp_rows[static_cast<size_t>(gi) * 64 + i] = make_int2(x, h.deg[x]);
-      for (int t = 0; t < h.deg[x]; ++t)
-        nb[static_cast<size_t>(grp[gi].x) + static_cast<size_t>(t) * 64 + i] = h.col[h.rowptr[x] + t];
+      for (int t = 0; t < h.deg[x]; ++t) {
+        const uint32_t id = static_cast<uint32_t>(h.col[h.rowptr[x] + t]);
+        uint32_t& w = nb[static_cast<size_t>(grp[gi].x) + static_cast<size_t>(t / K) * 64 + i];
+        if (K == 1) {
+          w = id;
+        } else {
+          const int sh = 16 * (t & 1);
+          w = (w & ~(0xFFFFu << sh)) | (id << sh);
+        }
+      }
     }
   }
   return SC_OK;
@@ -176,16 +193,23 @@ int class_of(const sc_batch* b, int n, int B, size_t tsize) {
   return 3;
 }
 
+// One persistent launch: the items of one (LDS class, block width) pair.
+struct Launch {
+  int cls, B;
+  int off, count;     // items [off, off + count) of the plan
+  size_t dyn;         // dynamic LDS bytes
+  int grid;
+  double cost;        // estimated, for the launch order
+};
+
 // Everything a run needs, prepared on the host before any device work.
 struct Plan {
   std::vector<int> graphs;             // subset, in batch order
   std::vector<int> L;                  // odd L per graph of the subset (0 = automatic)
   std::vector<double> lam;             // lambda* per graph of the subset (automatic only)
   std::vector<int> block;              // B per graph of the subset
-  std::vector<sc::BatchItem> items;    // grouped by class
-  int cls_off[kClasses + 1] = {0, 0, 0, 0, 0};
-  size_t cls_lds[kClasses] = {0, 0, 0, 0};
-  int cls_grid[kClasses] = {0, 0, 0, 0};
+  std::vector<sc::BatchItem> items;    // grouped by launch
+  std::vector<Launch> launches;        // most expensive first
   int64_t slab_elems = 0;
   int max_L = 255;
   double eps = 0.0;
@@ -229,53 +253,69 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
       est[q] = std::min<double>(P.max_L, std::max(1.0, t));
     }
   }
-  // items, longest first inside each class
+  // items grouped by (class, B), longest first inside each group
   struct Cand {
     double cost;
-    int cls;
+    int key;          // class * 7 + log2 B
     sc::BatchItem it;
   };
   std::vector<Cand> cand;
+  std::vector<double> key_cost(kLaunchMax, 0.0);
+  std::vector<size_t> key_lds(kLaunchMax, 0);
   for (size_t q = 0; q < ng; ++q) {
     const int gi = subset[q];
     const sc_graph* g = b->graphs[gi];
     const int n = g->d.n, B = P.block[q];
     const int cls = class_of(b, n, B, tsize);
+    const int key = cls * 7 + __builtin_ctz(static_cast<unsigned>(B));
     const double cost = est[q] * (static_cast<double>(g->d.nslots) + n) * std::sqrt(double(B));
-    for (int s0 = 0; s0 < n; s0 += B) cand.push_back({cost, cls, sc::BatchItem{gi, s0}});
+    for (int s0 = 0; s0 < n; s0 += B) cand.push_back({cost, key, sc::BatchItem{gi, s0}});
+    key_cost[key] += cost * ((n + B - 1) / B);
     if (cls == 3)   // rounded to 64 elements: every workgroup's slab stays 256-byte aligned
       P.slab_elems = std::max<int64_t>(P.slab_elems, (int64_t(state_bytes(n, B, tsize) / tsize) + 63) / 64 * 64);
-    else P.cls_lds[cls] = std::max(P.cls_lds[cls], state_bytes(n, B, tsize));
+    else
+      key_lds[key] = std::max(key_lds[key], state_bytes(n, B, tsize));
   }
   if (cand.size() > static_cast<size_t>(INT32_MAX)) return fail(SC_EINVAL, "too many items");
-  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& c) {
-    return a.cls != c.cls ? a.cls < c.cls : a.cost > c.cost;
+  // launches in decreasing total cost; items of a launch longest first
+  std::vector<int> order;
+  for (int k = 0; k < kLaunchMax; ++k)
+    if (key_cost[k] > 0.0) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key_cost[x] > key_cost[y]; });
+  std::vector<int> rank(kLaunchMax, 0);
+  for (size_t r = 0; r < order.size(); ++r) rank[order[r]] = static_cast<int>(r);
+  std::stable_sort(cand.begin(), cand.end(), [&](const Cand& x, const Cand& y) {
+    return x.key != y.key ? rank[x.key] < rank[y.key] : x.cost > y.cost;
   });
   P.items.resize(cand.size());
-  for (size_t i = 0; i < cand.size(); ++i) {
-    P.items[i] = cand[i].it;
-    P.cls_off[cand[i].cls + 1]++;
-  }
-  for (int c = 0; c < kClasses; ++c) P.cls_off[c + 1] += P.cls_off[c];
-  // grids: resident workgroups (occupancy), at most one per item
-  for (int c = 0; c < kClasses; ++c) {
-    const int nitems = P.cls_off[c + 1] - P.cls_off[c];
-    if (nitems == 0) continue;
-    const int nt = kClassThreads[c];
-    const bool lds = c < 3;
-    const void* fn = sc::batch_kernel_ptr<T>(nt, lds);
-    const size_t dyn = lds ? P.cls_lds[c] : 0;
+  for (size_t i = 0; i < cand.size(); ++i) P.items[i] = cand[i].it;
+  int off = 0;
+  for (int k : order) {
+    Launch l;
+    l.cls = k / 7;
+    l.B = 1 << (k % 7);
+    l.off = off;
+    l.count = 0;
+    for (size_t i = off; i < cand.size() && cand[i].key == k; ++i) ++l.count;
+    off += l.count;
+    l.dyn = l.cls < 3 ? key_lds[k] : 0;
+    l.cost = key_cost[k];
+    // grid: resident workgroups (occupancy), at most one per item
+    const int nt = kClassThreads[l.cls];
+    const bool lds = l.cls < 3;
+    const void* fn = sc::batch_kernel_ptr<T>(nt, lds, l.B);
     if (lds) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(dyn)));
+                                         static_cast<int>(l.dyn)));
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, dyn));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, l.dyn));
     if (per_cu < 1) per_cu = 1;
     int64_t grid = int64_t(per_cu) * b->cus;
     if (!lds) {
       const size_t sb = static_cast<size_t>(P.slab_elems) * tsize;
       grid = std::min<int64_t>(grid, std::max<int64_t>(1, int64_t(kSlabCap / sb)));
     }
-    P.cls_grid[c] = static_cast<int>(std::min<int64_t>(grid, nitems));
+    l.grid = static_cast<int>(std::min<int64_t>(grid, l.count));
+    P.launches.push_back(l);
   }
   return SC_OK;
 }
@@ -292,6 +332,7 @@ int stage_plan(sc_batch* b, const Plan& P) {
     d.n = g->d.n;
     d.B = 0;
     d.ngroups = b->ngroups[gi];
+    d.narrow = b->narrow[gi];
     d.rowptr = g->d.rowptr;
     d.col = g->d.col;
     d.slot_row = g->d.slot_row;
@@ -314,8 +355,11 @@ int stage_plan(sc_batch* b, const Plan& P) {
   if (!P.items.empty())
     HIP_TRY(hipMemcpy(b->d_items, P.items.data(), P.items.size() * sizeof(sc::BatchItem),
                       hipMemcpyHostToDevice));
-  if (P.cls_off[4] > P.cls_off[3]) {
-    const size_t need = static_cast<size_t>(P.cls_grid[3]) * P.slab_elems * tsize;
+  int slab_grid = 0;
+  for (const Launch& l : P.launches)
+    if (l.cls == 3) slab_grid = std::max(slab_grid, l.grid);
+  if (slab_grid > 0) {
+    const size_t need = static_cast<size_t>(slab_grid) * P.slab_elems * tsize;
     if (need > b->slab_bytes) {
       if (b->slabs) (void)hipFree(b->slabs);
       b->slabs = nullptr;
@@ -340,13 +384,12 @@ int enqueue_run(sc_batch* b, const Plan& P, double* const* outs, hipStream_t st,
     HIP_TRY(sc::launch_tau(g->d, P.L[q], P.eps, P.lam[q], P.max_L, ts, tr, st));
     HIP_TRY(sc::launch_gacc_init(g->d, ts, 1, b->gacc + b->slot_off[gi], st));
   }
-  HIP_TRY(sc::launch_fill_i32(b->d_misc, kClasses, 0, st));
+  HIP_TRY(sc::launch_fill_i32(b->d_misc, kLaunchMax, 0, st));
   if (kb) HIP_TRY(hipEventRecord(kb, st));
-  for (int c = 0; c < kClasses; ++c) {
-    const int nitems = P.cls_off[c + 1] - P.cls_off[c];
-    if (nitems == 0) continue;
-    HIP_TRY(sc::launch_batch<T>(kClassThreads[c], c < 3, P.cls_grid[c], c < 3 ? P.cls_lds[c] : 0,
-                                b->d_graphs, b->d_items + P.cls_off[c], nitems, b->d_misc + c,
+  for (size_t li = 0; li < P.launches.size(); ++li) {
+    const Launch& l = P.launches[li];
+    HIP_TRY(sc::launch_batch<T>(kClassThreads[l.cls], l.cls < 3, l.B, l.grid, l.dyn, b->d_graphs,
+                                b->d_items + l.off, l.count, b->d_misc + li,
                                 static_cast<T*>(b->slabs), P.slab_elems, st));
   }
   if (ke) HIP_TRY(hipEventRecord(ke, st));
@@ -355,12 +398,12 @@ int enqueue_run(sc_batch* b, const Plan& P, double* const* outs, hipStream_t st,
     HIP_TRY(sc::launch_combine(b->graphs[gi]->d, b->gacc + b->slot_off[gi], outs[q], st));
   }
   if (want_range) {
-    HIP_TRY(sc::launch_fill_i32(b->d_misc + kClasses, 1, INT32_MAX, st));
-    HIP_TRY(sc::launch_fill_i32(b->d_misc + kClasses + 1, 1, 0, st));
+    HIP_TRY(sc::launch_fill_i32(b->d_misc + kLaunchMax, 1, INT32_MAX, st));
+    HIP_TRY(sc::launch_fill_i32(b->d_misc + kLaunchMax + 1, 1, 0, st));
     for (size_t q = 0; q < P.graphs.size(); ++q) {
       const int gi = P.graphs[q];
       HIP_TRY(sc::launch_tau_range(b->tau_row + b->node_off[gi], b->graphs[gi]->d.n,
-                                   b->d_misc + kClasses, st));
+                                   b->d_misc + kLaunchMax, st));
     }
   }
   return SC_OK;
@@ -465,7 +508,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
                                b->graphs[gi]->d.m * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   if (want_range)
-    HIP_TRY(hipMemcpyAsync(b->h_misc, b->d_misc + kClasses, 2 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(b->h_misc, b->d_misc + kLaunchMax, 2 * sizeof(int32_t),
                            hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(t1, st));
   if (!dev_ptrs || want_range || timing) HIP_TRY(hipEventSynchronize(t1));
@@ -485,9 +528,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
       if (B != B0) B0 = -1;
     s.block = B0;
     for (double l : P.lam) s.lambda_star = std::max(s.lambda_star, l);
-    int launches = 0;
-    for (int c = 0; c < kClasses; ++c) launches += P.cls_off[c + 1] > P.cls_off[c] ? 1 : 0;
-    s.prop_launches = launches;
+    s.prop_launches = static_cast<int64_t>(P.launches.size());
     s.prop_ms = kms;
     float tms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&tms, t0, t1));
@@ -536,6 +577,7 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
   b->grp.assign(G, nullptr);
   b->grp_rows.assign(G, nullptr);
   b->ngroups.assign(G, 0);
+  b->narrow.assign(G, 0);
   b->dmin.assign(G, 0);
   b->graphs.assign(G, nullptr);
   for (int gi = 0; gi < G; ++gi) {
@@ -545,9 +587,9 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
       fail(rc, "graph " + std::to_string(gi) + ": " + sc_last_error());
       return bail(rc);
     }
-    std::vector<int32_t> nbh;
+    std::vector<uint32_t> nbh;
     std::vector<int2> grph, rowsh;
-    rc = build_slices(h, nbh, grph, rowsh);
+    rc = build_slices(h, nbh, grph, rowsh, &b->narrow[gi]);
     if (rc) return bail(rc);
     b->ngroups[gi] = static_cast<int32_t>(grph.size());
     b->dmin[gi] = *std::min_element(h.deg.begin(), h.deg.end());
@@ -575,7 +617,7 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
                                          std::max<int64_t>(1, b->edge_off[G]) * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_misc), 2 * sizeof(int32_t));
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_graphs, G);
-  if (e == hipSuccess) e = sc::dev_alloc(&b->d_misc, kClasses + 2);
+  if (e == hipSuccess) e = sc::dev_alloc(&b->d_misc, kLaunchMax + 2);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   int lds = 0, cus = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);

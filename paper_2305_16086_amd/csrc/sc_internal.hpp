@@ -76,14 +76,16 @@ struct DeviceGraph {
 
 // One graph of a batch as the persistent kernel sees it (device pointers).
 // Rows sorted by degree (descending) form groups of 64; group gi stores its
-// neighbour lists column-major at nb[grp[gi].x + t * 64 + i] for t <
-// grp[gi].y (its largest degree), padded with the zero row n; grp_rows[gi *
-// 64 + i] = (row, degree), (n, 0) past the last row.
+// neighbour lists column-major in 32-bit words, word w of row i at
+// nb[grp[gi].x + w * 64 + i] for w < W / K, W = grp[gi].y (its largest
+// degree) rounded up to kBatchSlots, K = 2 ids of 16 bits per word when narrow (n < 65535),
+// else K = 1; padded with the zero row n, and kBatchWordPad words past the
+// last group; grp_rows[gi * 64 + i] = (row, degree), (n, 0) past the last row.
 struct BatchGraph {
   int32_t n = 0;
   int32_t B = 0;                    // source-block width of this graph's items
   int32_t ngroups = 0;
-  int32_t pad = 0;
+  int32_t narrow = 0;               // 1: two 16-bit ids per neighbour word
   const int32_t* rowptr = nullptr;
   const int32_t* col = nullptr;
   const int32_t* slot_row = nullptr;
@@ -91,11 +93,14 @@ struct BatchGraph {
   const int32_t* tau_row = nullptr;
   const float* inv_f = nullptr;
   const double* inv_d = nullptr;
-  const int32_t* nb = nullptr;
+  const uint32_t* nb = nullptr;
   const int2* grp = nullptr;
   const int2* grp_rows = nullptr;
   double* gacc = nullptr;
 };
+
+constexpr int kBatchSlots = 8;          // neighbour slots per gather batch (group widths padded to it)
+constexpr int kBatchWordPad = 8 * 64;   // spare words after the last group
 
 struct BatchItem {
   int32_t graph;
@@ -218,16 +223,16 @@ hipError_t launch_multi_dot(const double* V, int ncols, int64_t ld, const double
 hipError_t launch_multi_axpy(const double* V, int ncols, int64_t ld, const double* h,
                              double* w, int64_t n, hipStream_t st);
 
-// Persistent batch kernel: workgroups of nt threads (256, 512, 1024) take
-// items from *ticket (zero before the launch) until it passes nitems.  lds:
-// block states in dyn_lds bytes of dynamic LDS, else in slabs of slab_elems
-// elements per workgroup.
+// Persistent batch kernel for items of block width B: workgroups of nt
+// threads (256, 512, 1024) take items from *ticket (zero before the launch)
+// until it passes nitems.  lds: block states in dyn_lds bytes of dynamic
+// LDS, else in slabs of slab_elems elements per workgroup (nt = 256).
 template <typename T>
-hipError_t launch_batch(int nt, bool lds, int grid, size_t dyn_lds, const BatchGraph* graphs,
+hipError_t launch_batch(int nt, bool lds, int B, int grid, size_t dyn_lds, const BatchGraph* graphs,
                         const BatchItem* items, int nitems, int* ticket, T* slabs,
                         int64_t slab_elems, hipStream_t st);
 template <typename T>
-const void* batch_kernel_ptr(int nt, bool lds);
+const void* batch_kernel_ptr(int nt, bool lds, int B);
 hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st);
 // mm[0] = min(mm[0], min tau_row), mm[1] = max(mm[1], max tau_row)
 hipError_t launch_tau_range(const int32_t* tau_row, int64_t count, int32_t* mm, hipStream_t st);
