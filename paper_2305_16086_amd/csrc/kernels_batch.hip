@@ -22,6 +22,7 @@
 // 64-slot pieces; giant rows in chunks), so with B in {16, 32, 64} a graph's
 // results are bitwise equal to the single-graph path.
 #include "sc_internal.hpp"
+#include "tau.hpp"
 
 namespace sc {
 
@@ -37,11 +38,28 @@ __device__ inline Pack<T, V> load_pack(const T* p) {
   return *reinterpret_cast<const Pack<T, V>*>(p);
 }
 
+// Pointers the hot loop reads are cast to the global address space so that
+// their loads are global (not flat) loads: flat loads also count against the
+// LDS counter, which would make every wait for an LDS gather wait for the
+// prefetched neighbour words as well.
+#define SC_GLOBAL __attribute__((address_space(1)))
+template <typename P>
+__device__ inline const SC_GLOBAL P* gptr(const P* p) {
+  return (const SC_GLOBAL P*)p;
+}
+
 __device__ inline int wave_max_i(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
   return v;
 }
+
+template <typename T>
+__device__ inline const T* grp_inv_of(const BatchGraph& g);
+template <>
+__device__ inline const float* grp_inv_of<float>(const BatchGraph& g) { return g.grp_invf; }
+template <>
+__device__ inline const double* grp_inv_of<double>(const BatchGraph& g) { return g.grp_invd; }
 
 template <typename T>
 __device__ inline const T* inv_of(const BatchGraph& g);
@@ -64,11 +82,17 @@ __device__ inline void tree(T (&acc)[G][V], T (&out)[V]) {
   for (int e = 0; e < V; ++e) out[e] = acc[0][e];
 }
 
-// Slot t of a lane's row: word t / K of its column of the group (K = 2: two
-// 16-bit ids per word, low half first).
+// Where a lane's row keeps its neighbour ids: the first kBatchSlots in its
+// record, the rest column-major in nb from its column base.
+struct RowIds {
+  const SC_GLOBAL uint32_t* rec;   // record words 4 ..
+  const SC_GLOBAL uint32_t* col;   // nb + column base
+};
+
+// Slot t of a lane's row (K = 2: two 16-bit ids per word, low half first).
 template <int K>
-__device__ inline int slot_index(const uint32_t* __restrict__ nw, int t) {
-  const uint32_t w = nw[(t / K) * 64];
+__device__ inline int slot_index(const RowIds& r, int t) {
+  const uint32_t w = t < kBatchSlots ? r.rec[t / K] : r.col[((t - kBatchSlots) / K) * 64];
   return K == 1 ? static_cast<int>(w) : static_cast<int>((w >> (16 * (t & 1))) & 0xFFFFu);
 }
 
@@ -76,8 +100,7 @@ __device__ inline int slot_index(const uint32_t* __restrict__ nw, int t) {
 // four interleaved 64-slot pieces (piece p belongs to part p mod 4), each part
 // with G interleaved partial sums, parts added in order.
 template <typename T, int B, int V, int G, int K>
-__device__ inline void chunk_sum(const uint32_t* __restrict__ nw, const T* Y, int cv, int b, int e,
-                                 T (&tot)[V]) {
+__device__ inline void chunk_sum(const RowIds& ids, const T* Y, int cv, int b, int e, T (&tot)[V]) {
 #pragma unroll 1
   for (int w = 0; w < kWavesPerBlock; ++w) {
     T acc[G][V];
@@ -92,8 +115,7 @@ __device__ inline void chunk_sum(const uint32_t* __restrict__ nw, const T* Y, in
         for (int g = 0; g < G; ++g) {
           const int t = t0 + g;
           if (t < pe) {
-            const int u = slot_index<K>(nw, t);
-            const Pack<T, V> p = load_pack<T, V>(Y + static_cast<size_t>(u) * B + cv);
+            const Pack<T, V> p = load_pack<T, V>(Y + static_cast<size_t>(slot_index<K>(ids, t)) * B + cv);
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[g][q] += p.v[q];
           }
@@ -110,8 +132,7 @@ __device__ inline void chunk_sum(const uint32_t* __restrict__ nw, const T* Y, in
 // Rows of more than kChunk neighbours (and lanes sharing their pass) in the
 // order of the single-graph workgroup tasks; giant rows chunk by chunk.
 template <typename T, int B, int V, int G, int K>
-__device__ inline void heavy_sum(const uint32_t* __restrict__ nw, const T* Yp, int cv, int d,
-                                 T (&out)[V]) {
+__device__ inline void heavy_sum(const RowIds& ids, const T* Yp, int cv, int d, T (&out)[V]) {
   if (d <= kChunk) {
     T acc[G][V];
 #pragma unroll
@@ -123,7 +144,7 @@ __device__ inline void heavy_sum(const uint32_t* __restrict__ nw, const T* Yp, i
       for (int gg = 0; gg < G; ++gg) {
         const int t = t0 + gg;
         if (t < d) {
-          const Pack<T, V> pk = load_pack<T, V>(Yp + static_cast<size_t>(slot_index<K>(nw, t)) * B + cv);
+          const Pack<T, V> pk = load_pack<T, V>(Yp + static_cast<size_t>(slot_index<K>(ids, t)) * B + cv);
 #pragma unroll
           for (int q = 0; q < V; ++q) acc[gg][q] += pk.v[q];
         }
@@ -131,13 +152,13 @@ __device__ inline void heavy_sum(const uint32_t* __restrict__ nw, const T* Yp, i
     }
     tree<T, G, V>(acc, out);
   } else if (d <= kGiant) {
-    chunk_sum<T, B, V, G, K>(nw, Yp, cv, 0, d, out);
+    chunk_sum<T, B, V, G, K>(ids, Yp, cv, 0, d, out);
   } else {
 #pragma unroll
     for (int q = 0; q < V; ++q) out[q] = T(0);
     for (int b = 0; b < d; b += kGiantChunk) {
       T c[V];
-      chunk_sum<T, B, V, G, K>(nw, Yp, cv, b, min(b + kGiantChunk, d), c);
+      chunk_sum<T, B, V, G, K>(ids, Yp, cv, b, min(b + kGiantChunk, d), c);
 #pragma unroll
       for (int q = 0; q < V; ++q) out[q] += c[q];
     }
@@ -151,8 +172,7 @@ static_assert(kBatchSlots == 8, "gather_batch is written for 8 slots");
 // holds a real neighbour or the zero row n, so no slot needs a mask; slot s
 // goes to partial sum s mod G (the single-graph order).
 template <typename T, int B, int V, int G, int K>
-__device__ inline void gather_batch(const uint32_t (&wd)[kBatchSlots / K], const T* Yp, int cv,
-                                    T (&acc)[G][V]) {
+__device__ inline void gather_batch(const uint32_t* wd, const T* Yp, int cv, T (&acc)[G][V]) {
   int u[kBatchSlots];
 #pragma unroll
   for (int s = 0; s < kBatchSlots; ++s)
@@ -166,11 +186,35 @@ __device__ inline void gather_batch(const uint32_t (&wd)[kBatchSlots / K], const
     for (int e = 0; e < V; ++e) acc[s % G][e] += pk[s].v[e];
 }
 
+// A row record: (row, degree, column base, 0) and the first kBatchSlots ids.
+template <int K>
+struct Rec {
+  static constexpr int kWords = 4 + kBatchSlots / K;
+  uint32_t w[kWords];
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ inline Rec<K> load_rec(const SC_GLOBAL uint32_t* rec, int r) {
+  Rec<K> out;
+  const SC_GLOBAL u32x4* p = (const SC_GLOBAL u32x4*)(rec + static_cast<size_t>(r) * Rec<K>::kWords);
+#pragma unroll
+  for (int j = 0; j < Rec<K>::kWords / 4; ++j) {
+    const u32x4 v = p[j];
+    out.w[4 * j] = v.x;
+    out.w[4 * j + 1] = v.y;
+    out.w[4 * j + 2] = v.z;
+    out.w[4 * j + 3] = v.w;
+  }
+  return out;
+}
+
 // Propagation of one graph's block state: Yn = P Yp for all rows.  Each wave
 // walks its passes (group gi = wave, wave + NW, ...; LR passes per group) and
-// fetches the next pass's row descriptors and first neighbour words before
-// it gathers the current pass.  Rows are sorted by degree, so a pass's width
-// is the degree of its first row (lane 0).
+// loads the next pass's row records (which carry the first neighbour ids)
+// before it gathers the current pass.  Rows are sorted by degree, so a pass's
+// width is the degree of its first row (lane 0).
 template <typename T, int B, int NT, int K>
 __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   constexpr int V = (B * sizeof(T) < 16) ? B : static_cast<int>(16 / sizeof(T));
@@ -181,62 +225,59 @@ __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   constexpr int NW = NT / 64;
   constexpr int kW = kBatchSlots / K; // words per batch
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = g.n;
-  const T* __restrict__ inv = inv_of<T>(g);
-  const uint32_t* __restrict__ nbw = g.nb;
+  const SC_GLOBAL uint32_t* __restrict__ nbw = gptr(g.nb);
+  const SC_GLOBAL uint32_t* __restrict__ recs = gptr(g.rec);
+  const SC_GLOBAL T* __restrict__ ginv = gptr(grp_inv_of<T>(g));
   const int cv = (lane % LR) * V;
   const int nq = wave < g.ngroups ? ((g.ngroups - 1 - wave) / NW + 1) * LR : 0;
-  uint32_t wn[kW];
-  int2 rdn = make_int2(n, 0);
-  int offn = 0;
+  Rec<K> rn;
+  T invn = T(0);
+  int rin = 0;
   if (nq > 0) {
-    const int i = lane / LR;
-    offn = g.grp[wave].x + i;
-    rdn = g.grp_rows[wave * 64 + i];
-#pragma unroll
-    for (int w = 0; w < kW; ++w) wn[w] = nbw[offn + w * 64];
+    rin = wave * 64 + lane / LR;
+    rn = load_rec<K>(recs, rin);
+    invn = ginv[rin];
   }
   for (int q = 0; q < nq; ++q) {
-    uint32_t wc[kW];
-#pragma unroll
-    for (int w = 0; w < kW; ++w) wc[w] = wn[w];
-    const int x = rdn.x;
-    const int d = rdn.y;
-    const int off = offn;
+    const Rec<K> rc = rn;
+    const T sc = invn;
+    const int ri = rin;
     if (q + 1 < nq) {
       const int gi = wave + ((q + 1) / LR) * NW;
-      const int i = ((q + 1) % LR) * RPP + lane / LR;
-      offn = g.grp[gi].x + i;
-      rdn = g.grp_rows[gi * 64 + i];
-#pragma unroll
-      for (int w = 0; w < kW; ++w) wn[w] = nbw[offn + w * 64];
+      rin = gi * 64 + ((q + 1) % LR) * RPP + lane / LR;
+      rn = load_rec<K>(recs, rin);
+      invn = ginv[rin];
     }
+    const int x = static_cast<int>(rc.w[0]);
+    const int d = static_cast<int>(rc.w[1]);
+    const int cb = static_cast<int>(rc.w[2]);
     const int wmax = __builtin_amdgcn_readfirstlane(d);
-    const uint32_t* __restrict__ nw = nbw + off;
     T out[V];
     if (kEmul && wmax > kChunk) {
-      heavy_sum<T, B, V, G, K>(nw, Yp, cv, d, out);
+      const RowIds ids{recs + static_cast<size_t>(ri) * Rec<K>::kWords + 4, nbw + cb};
+      heavy_sum<T, B, V, G, K>(ids, Yp, cv, d, out);
     } else {
       T acc[G][V];
 #pragma unroll
       for (int gg = 0; gg < G; ++gg)
 #pragma unroll
         for (int e = 0; e < V; ++e) acc[gg][e] = T(0);
-      gather_batch<T, B, V, G, K>(wc, Yp, cv, acc);
+      gather_batch<T, B, V, G, K>(rc.w + 4, Yp, cv, acc);
+      const SC_GLOBAL uint32_t* __restrict__ nc = nbw + cb;
       for (int t0 = kBatchSlots; t0 < wmax; t0 += kBatchSlots) {
         uint32_t wd[kW];
 #pragma unroll
-        for (int w = 0; w < kW; ++w) wd[w] = nw[(t0 / K + w) * 64];
+        for (int w = 0; w < kW; ++w) wd[w] = nc[((t0 - kBatchSlots) / K + w) * 64];
         gather_batch<T, B, V, G, K>(wd, Yp, cv, acc);
       }
       tree<T, G, V>(acc, out);
     }
     if (x < n) {
-      const T s = inv[x];
       Pack<T, V> o;
 #pragma unroll
-      for (int e = 0; e < V; ++e) o.v[e] = out[e] * s;
+      for (int e = 0; e < V; ++e) o.v[e] = out[e] * sc;
       *reinterpret_cast<Pack<T, V>*>(Yn + static_cast<size_t>(x) * B + cv) = o;
     }
   }
@@ -353,12 +394,66 @@ __global__ void k_fill_i32(int32_t* p, int count, int value) {
   if (i < count) p[i] = value;
 }
 
-// min / max of tau_row over a range (integer atomics: order-independent)
-__global__ void k_tau_range(const int32_t* __restrict__ tau_row, int64_t count, int32_t* mm) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  atomicMin(&mm[0], tau_row[i]);
-  atomicMax(&mm[1], tau_row[i]);
+// index of the graph holding global index i: off[g] <= i < off[g + 1]
+__device__ inline int graph_of(const int64_t* __restrict__ off, int G, int64_t i) {
+  int lo = 0, hi = G;   // off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_batch_prologue(const BatchGraph* __restrict__ graphs,
+                                 const int64_t* __restrict__ node_off, int G, int64_t total,
+                                 int32_t* mm) {
+  const int64_t X = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int tlo = INT_MAX, thi = 0;
+  if (X < total) {
+    const int gi = graph_of(node_off, G, X);
+    const BatchGraph& g = graphs[gi];
+    if (g.active) {
+      const int x = static_cast<int>(X - node_off[gi]);
+      const double di = static_cast<double>(g.deg[x]);
+      const double eps_tau = g.eps;
+      int tmax = 0;
+      for (int k = g.rowptr[x]; k < g.rowptr[x + 1]; ++k) {
+        const int j = g.col[k];
+        const int t = tau_of(g.L, di, static_cast<double>(g.deg[j]), eps_tau, g.lam, g.max_L);
+        const_cast<int32_t*>(g.tau_slot)[k] = t;
+        tmax = t > tmax ? t : tmax;
+        double v = g.inv_d[x];                       // l = 0: p_0(x,x)/d_x
+        if (t >= 1) v -= g.inv_d[j] * g.inv_d[x];    // l = 1: -p_1(j,x)/d_x
+        g.gacc[k] = v;
+      }
+      const_cast<int32_t*>(g.tau_row)[x] = tmax;
+      tlo = tmax;
+      thi = tmax;
+    }
+  }
+  if (mm) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      tlo = min(tlo, __shfl_xor(tlo, off, 64));
+      thi = max(thi, __shfl_xor(thi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (tlo != INT_MAX) atomicMin(&mm[0], tlo);
+      atomicMax(&mm[1], thi);
+    }
+  }
+}
+
+__global__ void k_batch_combine(const BatchGraph* __restrict__ graphs,
+                                const int64_t* __restrict__ edge_off, int G, int64_t total) {
+  const int64_t E = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (E >= total) return;
+  const int gi = graph_of(edge_off, G, E);
+  const BatchGraph& g = graphs[gi];
+  if (!g.active) return;
+  const int e = static_cast<int>(E - edge_off[gi]);
+  g.out[e] = g.gacc[g.half_slot[e]] + g.gacc[g.half_slot[e + g.m]];
 }
 
 template <typename T, int NT, bool kLds, int B>
@@ -438,9 +533,19 @@ hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_tau_range(const int32_t* tau_row, int64_t count, int32_t* mm, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  k_tau_range<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(tau_row, count, mm);
+hipError_t launch_batch_prologue(const BatchGraph* graphs, const int64_t* node_off, int G,
+                                 int64_t total_rows, int32_t* mm, hipStream_t st) {
+  if (total_rows <= 0) return hipSuccess;
+  k_batch_prologue<<<static_cast<unsigned>((total_rows + 255) / 256), 256, 0, st>>>(
+      graphs, node_off, G, total_rows, mm);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(const BatchGraph* graphs, const int64_t* edge_off, int G,
+                                int64_t total_edges, hipStream_t st) {
+  if (total_edges <= 0) return hipSuccess;
+  k_batch_combine<<<static_cast<unsigned>((total_edges + 255) / 256), 256, 0, st>>>(
+      graphs, edge_off, G, total_edges);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 // kGiant neighbours is cut into workgroup chunks whose partial sums a fix-up
 // pass adds in chunk order.
 #include "sc_internal.hpp"
+#include "tau.hpp"
 
 #include <cfloat>
 #include <climits>
@@ -39,13 +40,6 @@ __global__ void k_gacc_init(int64_t nslots, const int32_t* __restrict__ slot_row
 }
 
 // ------------------------------------------------------------------ truncation lengths
-__device__ inline int odd_at_least(double f) {
-  long long k = static_cast<long long>(ceil(f));
-  if (k < 1) k = 1;
-  if ((k & 1) == 0) ++k;
-  return k > INT_MAX ? INT_MAX : static_cast<int>(k);
-}
-
 __global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                       const int32_t* __restrict__ deg, int L, double eps_tau, double lam,
                       int max_L, int32_t* __restrict__ tau_slot, int32_t* __restrict__ tau_row) {
@@ -54,16 +48,7 @@ __global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* 
   int tmax = 0;
   const double di = static_cast<double>(deg[x]);
   for (int k = rowptr[x]; k < rowptr[x + 1]; ++k) {
-    int t;
-    if (L > 0) {
-      t = L;
-    } else {
-      const double dj = static_cast<double>(deg[col[k]]);
-      const double num = 1.0 / di + 1.0 / dj - 2.0 / (di * dj);
-      const double f = ceil(log(num / (eps_tau * (1.0 - lam * lam))) / log(1.0 / lam) - 1.0);
-      t = odd_at_least(f);
-      if (t > max_L) t = max_L;
-    }
+    const int t = tau_of(L, di, static_cast<double>(deg[col[k]]), eps_tau, lam, max_L);
     tau_slot[k] = t;
     tmax = t > tmax ? t : tmax;
   }

@@ -40,7 +40,9 @@ struct sc_batch {
   // sliced neighbour lists (built once)
   std::vector<uint32_t*> nb;
   std::vector<int32_t> narrow;
-  std::vector<int2*> grp, grp_rows;
+  std::vector<uint32_t*> rec;
+  std::vector<float*> grp_invf;
+  std::vector<double*> grp_invd;
   std::vector<int32_t> ngroups;
   // run buffers (batch-wide, indexed by the offsets)
   int32_t* tau_slot = nullptr;
@@ -49,6 +51,8 @@ struct sc_batch {
   double* out_dev = nullptr;       // host-output runs: results before the copy
   double* out_pinned = nullptr;    // pinned staging of out_dev
   sc::BatchGraph* d_graphs = nullptr;
+  int64_t* d_node_off = nullptr;   // [G + 1]
+  int64_t* d_edge_off = nullptr;   // [G + 1]
   sc::BatchItem* d_items = nullptr;
   size_t items_cap = 0;
   int32_t* d_misc = nullptr;       // [0, kLaunchMax): tickets; [kLaunchMax, +2): tau min / max
@@ -81,8 +85,9 @@ struct sc_batch {
     }
     graphs.clear();
     for (auto*& p : nb) sc::dev_free(p);
-    for (auto*& p : grp) sc::dev_free(p);
-    for (auto*& p : grp_rows) sc::dev_free(p);
+    for (auto*& p : rec) sc::dev_free(p);
+    for (auto*& p : grp_invf) sc::dev_free(p);
+    for (auto*& p : grp_invd) sc::dev_free(p);
     sc::dev_free(tau_slot);
     sc::dev_free(tau_row);
     sc::dev_free(gacc);
@@ -92,6 +97,8 @@ struct sc_batch {
     if (h_misc) (void)hipHostFree(h_misc);
     h_misc = nullptr;
     sc::dev_free(d_graphs);
+    sc::dev_free(d_node_off);
+    sc::dev_free(d_edge_off);
     sc::dev_free(d_items);
     sc::dev_free(d_misc);
     if (slabs) (void)hipFree(slabs);
@@ -103,46 +110,65 @@ struct sc_batch {
 
 namespace {
 
-// Rows sorted by degree (descending, ties by id) in groups of 64 with their
-// neighbour lists column-major in 32-bit words (two 16-bit ids per word when
-// n < 65535), padded with the zero row n, plus kBatchWordPad words at the end.
-int build_slices(const sc::HostCSR& h, std::vector<uint32_t>& nb, std::vector<int2>& grp,
-                 std::vector<int2>& grp_rows, int* narrow) {
+// Rows sorted by degree (descending, ties by id) in groups of 64: per row a
+// record (row, degree, column base, 0, first kBatchSlots neighbour ids) and
+// the remaining ids column-major in nb, two 16-bit ids per word when n <
+// 65535; padded with the zero row n; 1/degree per record in invf / invd.
+int build_slices(const sc::HostCSR& h, std::vector<uint32_t>& rec, std::vector<uint32_t>& nb,
+                 std::vector<float>& invf, std::vector<double>& invd, int* narrow) {
   const int n = h.n;
   const int K = n < 65535 ? 2 : 1;
+  const int KS = sc::kBatchSlots;
+  const int RW = 4 + KS / K;
   *narrow = K == 2 ? 1 : 0;
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return h.deg[a] > h.deg[b]; });
   const int ngroups = (n + 63) / 64;
-  grp.resize(ngroups);
-  grp_rows.assign(static_cast<size_t>(ngroups) * 64, make_int2(n, 0));
-  int64_t off = 0;
-  for (int gi = 0; gi < ngroups; ++gi) {
-    const int width = h.deg[order[gi * 64]];
-    const int64_t padded = (width + sc::kBatchSlots - 1) / sc::kBatchSlots * sc::kBatchSlots;
-    const int64_t words = padded / K;
-    if (off > INT32_MAX - words * 64 - sc::kBatchWordPad) return fail(SC_EINVAL, "batch graph too large");
-    grp[gi] = make_int2(static_cast<int>(off), width);
-    off += words * 64;
-  }
   const uint32_t pad_word = K == 2 ? (static_cast<uint32_t>(n) << 16) | static_cast<uint32_t>(n)
                                    : static_cast<uint32_t>(n);
-  nb.assign(static_cast<size_t>(off) + sc::kBatchWordPad, pad_word);
+  std::vector<int64_t> base(ngroups);
+  int64_t off = 0;
   for (int gi = 0; gi < ngroups; ++gi) {
-    for (int i = 0; i < 64 && gi * 64 + i < n; ++i) {
-      const int x = order[gi * 64 + i];
-      grp_rows[static_cast<size_t>(gi) * 64 + i] = make_int2(x, h.deg[x]);
-      for (int t = 0; t < h.deg[x]; ++t) {
+    const int64_t width = h.deg[order[gi * 64]];
+    const int64_t padded = (width + KS - 1) / KS * KS;
+    base[gi] = off;
+    off += (padded - KS) / K * 64;
+    if (off > INT32_MAX - sc::kBatchWordPad) return fail(SC_EINVAL, "batch graph too large");
+  }
+  nb.assign(static_cast<size_t>(off) + sc::kBatchWordPad, pad_word);
+  rec.assign(static_cast<size_t>(ngroups) * 64 * RW, pad_word);
+  invf.assign(static_cast<size_t>(ngroups) * 64, 0.0f);
+  invd.assign(static_cast<size_t>(ngroups) * 64, 0.0);
+  auto put = [&](uint32_t& w, int t, uint32_t id) {
+    if (K == 1) {
+      w = id;
+    } else {
+      const int sh = 16 * (t & 1);
+      w = (w & ~(0xFFFFu << sh)) | (id << sh);
+    }
+  };
+  for (int gi = 0; gi < ngroups; ++gi) {
+    for (int i = 0; i < 64; ++i) {
+      const size_t r = static_cast<size_t>(gi) * 64 + i;
+      uint32_t* rr = &rec[r * RW];
+      const bool real = gi * 64 + i < n;
+      const int x = real ? order[gi * 64 + i] : n;
+      const int dx = real ? h.deg[x] : 0;
+      rr[0] = static_cast<uint32_t>(x);
+      rr[1] = static_cast<uint32_t>(dx);
+      rr[2] = static_cast<uint32_t>(base[gi] + i);
+      rr[3] = 0;
+      if (!real) continue;
+      invf[r] = h.inv_f[x];
+      invd[r] = h.inv_d[x];
+      for (int t = 0; t < dx; ++t) {
         const uint32_t id = static_cast<uint32_t>(h.col[h.rowptr[x] + t]);
-        uint32_t& w = nb[static_cast<size_t>(grp[gi].x) + static_cast<size_t>(t / K) * 64 + i];
-        if (K == 1) {
-          w = id;
-        } else {
-          const int sh = 16 * (t & 1);
-          w = (w & ~(0xFFFFu << sh)) | (id << sh);
-        }
+        if (t < KS)
+          put(rr[4 + t / K], t, id);
+        else
+          put(nb[static_cast<size_t>(base[gi] + i) + static_cast<size_t>((t - KS) / K) * 64], t, id);
       }
     }
   }
@@ -322,7 +348,7 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
 
 // Device tables and buffers for plan P (host -> device copies, synchronous).
 template <typename T>
-int stage_plan(sc_batch* b, const Plan& P) {
+int stage_plan(sc_batch* b, const Plan& P, double* const* outs) {
   const size_t tsize = sizeof(T);
   const int G = static_cast<int>(b->graphs.size());
   std::vector<sc::BatchGraph> tab(G);
@@ -341,11 +367,24 @@ int stage_plan(sc_batch* b, const Plan& P) {
     d.inv_f = g->d.inv_deg_f;
     d.inv_d = g->d.inv_deg_d;
     d.nb = b->nb[gi];
-    d.grp = b->grp[gi];
-    d.grp_rows = b->grp_rows[gi];
+    d.rec = b->rec[gi];
+    d.grp_invf = b->grp_invf[gi];
+    d.grp_invd = b->grp_invd[gi];
     d.gacc = b->gacc + b->slot_off[gi];
+    d.deg = g->d.deg;
+    d.half_slot = g->d.half_slot;
+    d.m = static_cast<int32_t>(g->d.m);
+    d.max_L = P.max_L;
+    d.eps = P.eps;
   }
-  for (size_t q = 0; q < P.graphs.size(); ++q) tab[P.graphs[q]].B = P.block[q];
+  for (size_t q = 0; q < P.graphs.size(); ++q) {
+    sc::BatchGraph& d = tab[P.graphs[q]];
+    d.B = P.block[q];
+    d.L = P.L[q];
+    d.lam = P.lam[q];
+    d.out = outs[q];
+    d.active = 1;
+  }
   HIP_TRY(hipMemcpy(b->d_graphs, tab.data(), G * sizeof(sc::BatchGraph), hipMemcpyHostToDevice));
   if (P.items.size() > b->items_cap) {
     sc::dev_free(b->d_items);
@@ -374,17 +413,16 @@ int stage_plan(sc_batch* b, const Plan& P) {
 // Device work of plan P on stream st (no allocation, no host synchronisation,
 // no memset: safe to capture).  outs[q]: device output of graph P.graphs[q].
 template <typename T>
-int enqueue_run(sc_batch* b, const Plan& P, double* const* outs, hipStream_t st,
-                hipEvent_t kb, hipEvent_t ke, bool want_range) {
-  for (size_t q = 0; q < P.graphs.size(); ++q) {
-    const int gi = P.graphs[q];
-    const sc_graph* g = b->graphs[gi];
-    int32_t* ts = b->tau_slot + b->slot_off[gi];
-    int32_t* tr = b->tau_row + b->node_off[gi];
-    HIP_TRY(sc::launch_tau(g->d, P.L[q], P.eps, P.lam[q], P.max_L, ts, tr, st));
-    HIP_TRY(sc::launch_gacc_init(g->d, ts, 1, b->gacc + b->slot_off[gi], st));
-  }
+int enqueue_run(sc_batch* b, const Plan& P, hipStream_t st, hipEvent_t kb, hipEvent_t ke,
+                bool want_range) {
+  const int G = static_cast<int>(b->graphs.size());
+  int32_t* mm = want_range ? b->d_misc + kLaunchMax : nullptr;
   HIP_TRY(sc::launch_fill_i32(b->d_misc, kLaunchMax, 0, st));
+  if (mm) {
+    HIP_TRY(sc::launch_fill_i32(mm, 1, INT32_MAX, st));
+    HIP_TRY(sc::launch_fill_i32(mm + 1, 1, 0, st));
+  }
+  HIP_TRY(sc::launch_batch_prologue(b->d_graphs, b->d_node_off, G, b->node_off[G], mm, st));
   if (kb) HIP_TRY(hipEventRecord(kb, st));
   for (size_t li = 0; li < P.launches.size(); ++li) {
     const Launch& l = P.launches[li];
@@ -393,19 +431,7 @@ int enqueue_run(sc_batch* b, const Plan& P, double* const* outs, hipStream_t st,
                                 static_cast<T*>(b->slabs), P.slab_elems, st));
   }
   if (ke) HIP_TRY(hipEventRecord(ke, st));
-  for (size_t q = 0; q < P.graphs.size(); ++q) {
-    const int gi = P.graphs[q];
-    HIP_TRY(sc::launch_combine(b->graphs[gi]->d, b->gacc + b->slot_off[gi], outs[q], st));
-  }
-  if (want_range) {
-    HIP_TRY(sc::launch_fill_i32(b->d_misc + kLaunchMax, 1, INT32_MAX, st));
-    HIP_TRY(sc::launch_fill_i32(b->d_misc + kLaunchMax + 1, 1, 0, st));
-    for (size_t q = 0; q < P.graphs.size(); ++q) {
-      const int gi = P.graphs[q];
-      HIP_TRY(sc::launch_tau_range(b->tau_row + b->node_off[gi], b->graphs[gi]->d.n,
-                                   b->d_misc + kLaunchMax, st));
-    }
-  }
+  HIP_TRY(sc::launch_batch_combine(b->d_graphs, b->d_edge_off, G, b->edge_off[G], st));
   return SC_OK;
 }
 
@@ -446,7 +472,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   const bool reuse = replay && b->exec && key == b->exec_key;
   if (!reuse) {
     b->drop_exec();
-    rc = stage_plan<T>(b, P);
+    rc = stage_plan<T>(b, P, outs.data());
     if (rc) return rc;
   }
   hipEvent_t t0 = nullptr, t1 = nullptr, kb = nullptr, ke = nullptr;
@@ -471,7 +497,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     if (!reuse) {
       // record on the batch's own stream; the graph is then launched on st
       HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
-      rc = enqueue_run<T>(b, P, outs.data(), b->cap_stream, nullptr, nullptr, want_range);
+      rc = enqueue_run<T>(b, P, b->cap_stream, nullptr, nullptr, want_range);
       if (!dev_ptrs && rc == SC_OK) {
         for (int gi : P.graphs) {
           const hipError_t e = hipMemcpyAsync(
@@ -500,7 +526,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     }
     HIP_TRY(hipGraphLaunch(b->exec, st));
   } else {
-    rc = enqueue_run<T>(b, P, outs.data(), st, kb, ke, want_range);
+    rc = enqueue_run<T>(b, P, st, kb, ke, want_range);
     if (rc) return rc;
     if (!dev_ptrs)
       for (int gi : P.graphs)
@@ -574,8 +600,9 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
   b->slot_off.assign(G + 1, 0);
   b->edge_off.assign(G + 1, 0);
   b->nb.assign(G, nullptr);
-  b->grp.assign(G, nullptr);
-  b->grp_rows.assign(G, nullptr);
+  b->rec.assign(G, nullptr);
+  b->grp_invf.assign(G, nullptr);
+  b->grp_invd.assign(G, nullptr);
   b->ngroups.assign(G, 0);
   b->narrow.assign(G, 0);
   b->dmin.assign(G, 0);
@@ -587,19 +614,23 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
       fail(rc, "graph " + std::to_string(gi) + ": " + sc_last_error());
       return bail(rc);
     }
-    std::vector<uint32_t> nbh;
-    std::vector<int2> grph, rowsh;
-    rc = build_slices(h, nbh, grph, rowsh, &b->narrow[gi]);
+    std::vector<uint32_t> nbh, rech;
+    std::vector<float> invf;
+    std::vector<double> invd;
+    rc = build_slices(h, rech, nbh, invf, invd, &b->narrow[gi]);
     if (rc) return bail(rc);
-    b->ngroups[gi] = static_cast<int32_t>(grph.size());
+    b->ngroups[gi] = (h.n + 63) / 64;
     b->dmin[gi] = *std::min_element(h.deg.begin(), h.deg.end());
     hipError_t e = sc::dev_alloc(&b->nb[gi], nbh.size());
     if (e == hipSuccess) e = hipMemcpy(b->nb[gi], nbh.data(), nbh.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = sc::dev_alloc(&b->grp[gi], grph.size());
-    if (e == hipSuccess) e = hipMemcpy(b->grp[gi], grph.data(), grph.size() * sizeof(int2), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = sc::dev_alloc(&b->grp_rows[gi], rowsh.size());
+    if (e == hipSuccess) e = sc::dev_alloc(&b->rec[gi], rech.size());
+    if (e == hipSuccess) e = hipMemcpy(b->rec[gi], rech.data(), rech.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sc::dev_alloc(&b->grp_invf[gi], invf.size());
     if (e == hipSuccess)
-      e = hipMemcpy(b->grp_rows[gi], rowsh.data(), rowsh.size() * sizeof(int2), hipMemcpyHostToDevice);
+      e = hipMemcpy(b->grp_invf[gi], invf.data(), invf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sc::dev_alloc(&b->grp_invd[gi], invd.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(b->grp_invd[gi], invd.data(), invd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess)
       return bail(fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
                        std::string("batch upload: ") + hipGetErrorString(e)));
@@ -617,6 +648,12 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
                                          std::max<int64_t>(1, b->edge_off[G]) * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_misc), 2 * sizeof(int32_t));
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_graphs, G);
+  if (e == hipSuccess) e = sc::dev_alloc(&b->d_node_off, G + 1);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_node_off, b->node_off.data(), (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sc::dev_alloc(&b->d_edge_off, G + 1);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_edge_off, b->edge_off.data(), (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_misc, kLaunchMax + 2);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   int lds = 0, cus = 0;

@@ -75,12 +75,13 @@ struct DeviceGraph {
 };
 
 // One graph of a batch as the persistent kernel sees it (device pointers).
-// Rows sorted by degree (descending) form groups of 64; group gi stores its
-// neighbour lists column-major in 32-bit words, word w of row i at
-// nb[grp[gi].x + w * 64 + i] for w < W / K, W = grp[gi].y (its largest
-// degree) rounded up to kBatchSlots, K = 2 ids of 16 bits per word when narrow (n < 65535),
-// else K = 1; padded with the zero row n, and kBatchWordPad words past the
-// last group; grp_rows[gi * 64 + i] = (row, degree), (n, 0) past the last row.
+// Rows sorted by degree (descending) form groups of 64.  Row i of group gi
+// has a record rec[(gi * 64 + i) * RW ...] of RW = 4 + 8 / K words: (row,
+// degree, cb, 0) followed by its first kBatchSlots neighbour ids, K = 2 ids
+// of 16 bits per word when narrow (n < 65535), else K = 1; its slots from
+// kBatchSlots on sit column-major in nb, word w at nb[cb + w * 64].  Rows are
+// padded with the zero row n up to their group's largest degree rounded up
+// to kBatchSlots; records past the last row read (n, 0, 0, 0, n ...).
 struct BatchGraph {
   int32_t n = 0;
   int32_t B = 0;                    // source-block width of this graph's items
@@ -93,10 +94,21 @@ struct BatchGraph {
   const int32_t* tau_row = nullptr;
   const float* inv_f = nullptr;
   const double* inv_d = nullptr;
+  const uint32_t* rec = nullptr;
   const uint32_t* nb = nullptr;
-  const int2* grp = nullptr;
-  const int2* grp_rows = nullptr;
+  const float* grp_invf = nullptr;  // 1/degree of the records' rows (0 past the last)
+  const double* grp_invd = nullptr;
   double* gacc = nullptr;
+  // truncation and output of the run (prologue / epilogue kernels)
+  const int32_t* deg = nullptr;
+  const int32_t* half_slot = nullptr;
+  double* out = nullptr;            // device output, m doubles
+  int32_t m = 0;
+  int32_t L = 0;                    // odd uniform truncation, or 0: Theorem 3.2
+  int32_t max_L = 0;
+  int32_t active = 0;               // 1: graph takes part in the run
+  double eps = 0.0;
+  double lam = 0.0;
 };
 
 constexpr int kBatchSlots = 8;          // neighbour slots per gather batch (group widths padded to it)
@@ -234,7 +246,13 @@ hipError_t launch_batch(int nt, bool lds, int B, int grid, size_t dyn_lds, const
 template <typename T>
 const void* batch_kernel_ptr(int nt, bool lds, int B);
 hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st);
-// mm[0] = min(mm[0], min tau_row), mm[1] = max(mm[1], max tau_row)
-hipError_t launch_tau_range(const int32_t* tau_row, int64_t count, int32_t* mm, hipStream_t st);
+// Truncation per slot and row, and the closed-form l = 0, 1 terms, for every
+// row of the active graphs (node_off: G + 1 prefix of node counts); with mm,
+// mm[0] / mm[1] take the min / max of the rows' truncations.
+hipError_t launch_batch_prologue(const BatchGraph* graphs, const int64_t* node_off, int G,
+                                 int64_t total_rows, int32_t* mm, hipStream_t st);
+// out[e] = g(u_e, v_e) + g(v_e, u_e) for every edge of the active graphs.
+hipError_t launch_batch_combine(const BatchGraph* graphs, const int64_t* edge_off, int G,
+                                int64_t total_edges, hipStream_t st);
 
 }  // namespace sc
