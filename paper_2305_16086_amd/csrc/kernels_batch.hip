@@ -171,7 +171,7 @@ static_assert(kBatchSlots == 8, "gather_batch is written for 8 slots");
 // One batch of 8 slots (8 / K words): every slot inside the padded group width
 // holds a real neighbour or the zero row n, so no slot needs a mask; slot s
 // goes to partial sum s mod G (the single-graph order).
-template <typename T, int B, int V, int G, int K>
+template <typename T, int B, int V, int G, int K, bool kFirst>
 __device__ inline void gather_batch(const uint32_t* wd, const T* Yp, int cv, T (&acc)[G][V]) {
   int u[kBatchSlots];
 #pragma unroll
@@ -179,11 +179,17 @@ __device__ inline void gather_batch(const uint32_t* wd, const T* Yp, int cv, T (
     u[s] = K == 1 ? static_cast<int>(wd[s]) : static_cast<int>((wd[s / 2] >> (16 * (s & 1))) & 0xFFFFu);
   Pack<T, V> pk[kBatchSlots];
 #pragma unroll
-  for (int s = 0; s < kBatchSlots; ++s) pk[s] = load_pack<T, V>(Yp + static_cast<size_t>(u[s]) * B + cv);
+  for (int s = 0; s < kBatchSlots; ++s) pk[s] = load_pack<T, V>(Yp + static_cast<uint32_t>(u[s] * B + cv));
+  // the first batch starts each partial sum at its first value (0 + v == v)
 #pragma unroll
   for (int s = 0; s < kBatchSlots; ++s)
 #pragma unroll
-    for (int e = 0; e < V; ++e) acc[s % G][e] += pk[s].v[e];
+    for (int e = 0; e < V; ++e) {
+      if (kFirst && s < G)
+        acc[s][e] = pk[s].v[e];
+      else
+        acc[s % G][e] += pk[s].v[e];
+    }
 }
 
 // A row record: (row, degree, column base, 0) and the first kBatchSlots ids.
@@ -196,9 +202,9 @@ struct Rec {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int K>
-__device__ inline Rec<K> load_rec(const SC_GLOBAL uint32_t* rec, int r) {
+__device__ inline Rec<K> load_rec(const SC_GLOBAL uint32_t* rec, uint32_t r) {
   Rec<K> out;
-  const SC_GLOBAL u32x4* p = (const SC_GLOBAL u32x4*)(rec + static_cast<size_t>(r) * Rec<K>::kWords);
+  const SC_GLOBAL u32x4* p = (const SC_GLOBAL u32x4*)(rec + r * static_cast<uint32_t>(Rec<K>::kWords));
 #pragma unroll
   for (int j = 0; j < Rec<K>::kWords / 4; ++j) {
     const u32x4 v = p[j];
@@ -210,20 +216,54 @@ __device__ inline Rec<K> load_rec(const SC_GLOBAL uint32_t* rec, int r) {
   return out;
 }
 
+// One pass: the rows of one record per lane, gathered from Yp into Yn.
+template <typename T, int B, int K>
+__device__ __forceinline__ void row_pass(const Rec<K>& rc, T sc, uint32_t ri, int n,
+                                         const SC_GLOBAL uint32_t* __restrict__ recs,
+                                         const SC_GLOBAL uint32_t* __restrict__ nbw,
+                                         const T* Yp, T* Yn, int cv) {
+  constexpr int V = (B * sizeof(T) < 16) ? B : static_cast<int>(16 / sizeof(T));
+  constexpr int G = B >= 16 ? 64 / B : 1;
+  constexpr bool kEmul = B >= 16;     // single-graph kernels exist for these widths
+  constexpr int kW = kBatchSlots / K; // words per batch
+  const int x = static_cast<int>(rc.w[0]);
+  const int d = static_cast<int>(rc.w[1]);
+  const uint32_t cb = rc.w[2];
+  const int wmax = __builtin_amdgcn_readfirstlane(d);
+  T out[V];
+  if (kEmul && wmax > kChunk) {
+    const RowIds ids{recs + ri * static_cast<uint32_t>(Rec<K>::kWords) + 4, nbw + cb};
+    heavy_sum<T, B, V, G, K>(ids, Yp, cv, d, out);
+  } else {
+    T acc[G][V];
+    gather_batch<T, B, V, G, K, true>(rc.w + 4, Yp, cv, acc);
+    for (int t0 = kBatchSlots; t0 < wmax; t0 += kBatchSlots) {
+      uint32_t wd[kW];
+#pragma unroll
+      for (int w = 0; w < kW; ++w) wd[w] = nbw[cb + static_cast<uint32_t>(((t0 - kBatchSlots) / K + w) * 64)];
+      gather_batch<T, B, V, G, K, false>(wd, Yp, cv, acc);
+    }
+    tree<T, G, V>(acc, out);
+  }
+  if (x < n) {
+    Pack<T, V> o;
+#pragma unroll
+    for (int e = 0; e < V; ++e) o.v[e] = out[e] * sc;
+    *reinterpret_cast<Pack<T, V>*>(Yn + static_cast<uint32_t>(x * B + cv)) = o;
+  }
+}
+
 // Propagation of one graph's block state: Yn = P Yp for all rows.  Each wave
 // walks its passes (group gi = wave, wave + NW, ...; LR passes per group) and
 // loads the next pass's row records (which carry the first neighbour ids)
-// before it gathers the current pass.  Rows are sorted by degree, so a pass's
-// width is the degree of its first row (lane 0).
+// before it gathers the current pass; two register sets alternate.  Rows are
+// sorted by degree, so a pass's width is the degree of its first row (lane 0).
 template <typename T, int B, int NT, int K>
 __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   constexpr int V = (B * sizeof(T) < 16) ? B : static_cast<int>(16 / sizeof(T));
   constexpr int LR = B / V;           // lanes per row
   constexpr int RPP = 64 / LR;        // rows per pass
-  constexpr int G = B >= 16 ? 64 / B : 1;
-  constexpr bool kEmul = B >= 16;     // single-graph kernels exist for these widths
   constexpr int NW = NT / 64;
-  constexpr int kW = kBatchSlots / K; // words per batch
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = g.n;
@@ -232,54 +272,30 @@ __device__ inline void rows_step(const BatchGraph& g, const T* Yp, T* Yn) {
   const SC_GLOBAL T* __restrict__ ginv = gptr(grp_inv_of<T>(g));
   const int cv = (lane % LR) * V;
   const int nq = wave < g.ngroups ? ((g.ngroups - 1 - wave) / NW + 1) * LR : 0;
-  Rec<K> rn;
-  T invn = T(0);
-  int rin = 0;
+  // record index of pass q for this lane
+  auto rec_index = [&](int q) -> uint32_t {
+    return static_cast<uint32_t>((wave + (q / LR) * NW) * 64 + (q % LR) * RPP + lane / LR);
+  };
+  Rec<K> ra, rb;
+  T ia = T(0), ib = T(0);
+  uint32_t ja = 0, jb = 0;
   if (nq > 0) {
-    rin = wave * 64 + lane / LR;
-    rn = load_rec<K>(recs, rin);
-    invn = ginv[rin];
+    ja = rec_index(0);
+    ra = load_rec<K>(recs, ja);
+    ia = ginv[ja];
   }
-  for (int q = 0; q < nq; ++q) {
-    const Rec<K> rc = rn;
-    const T sc = invn;
-    const int ri = rin;
-    if (q + 1 < nq) {
-      const int gi = wave + ((q + 1) / LR) * NW;
-      rin = gi * 64 + ((q + 1) % LR) * RPP + lane / LR;
-      rn = load_rec<K>(recs, rin);
-      invn = ginv[rin];
-    }
-    const int x = static_cast<int>(rc.w[0]);
-    const int d = static_cast<int>(rc.w[1]);
-    const int cb = static_cast<int>(rc.w[2]);
-    const int wmax = __builtin_amdgcn_readfirstlane(d);
-    T out[V];
-    if (kEmul && wmax > kChunk) {
-      const RowIds ids{recs + static_cast<size_t>(ri) * Rec<K>::kWords + 4, nbw + cb};
-      heavy_sum<T, B, V, G, K>(ids, Yp, cv, d, out);
-    } else {
-      T acc[G][V];
-#pragma unroll
-      for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc[gg][e] = T(0);
-      gather_batch<T, B, V, G, K>(rc.w + 4, Yp, cv, acc);
-      const SC_GLOBAL uint32_t* __restrict__ nc = nbw + cb;
-      for (int t0 = kBatchSlots; t0 < wmax; t0 += kBatchSlots) {
-        uint32_t wd[kW];
-#pragma unroll
-        for (int w = 0; w < kW; ++w) wd[w] = nc[((t0 - kBatchSlots) / K + w) * 64];
-        gather_batch<T, B, V, G, K>(wd, Yp, cv, acc);
-      }
-      tree<T, G, V>(acc, out);
-    }
-    if (x < n) {
-      Pack<T, V> o;
-#pragma unroll
-      for (int e = 0; e < V; ++e) o.v[e] = out[e] * sc;
-      *reinterpret_cast<Pack<T, V>*>(Yn + static_cast<size_t>(x) * B + cv) = o;
-    }
+  // the loads for pass q + 1 are issued unconditionally (the last pass is
+  // reloaded at the end) so that the wait for pass q counts exactly
+  for (int q = 0; q < nq; q += 2) {
+    jb = rec_index(min(q + 1, nq - 1));
+    rb = load_rec<K>(recs, jb);
+    ib = ginv[jb];
+    row_pass<T, B, K>(ra, ia, ja, n, recs, nbw, Yp, Yn, cv);
+    if (q + 1 >= nq) break;
+    ja = rec_index(min(q + 2, nq - 1));
+    ra = load_rec<K>(recs, ja);
+    ia = ginv[ja];
+    row_pass<T, B, K>(rb, ib, jb, n, recs, nbw, Yp, Yn, cv);
   }
 }
 
