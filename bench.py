@@ -29,6 +29,19 @@ SEED = 1
 BLOCK = 64
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
+# HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
+# scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
+# kernel source they were taken on (first 16 hex digits of its SHA-256)
+PROP_TRAFFIC_BYTES = 421435333
+PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "d1911d48cdf5a77d")
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(ROOT, PROP_TRAFFIC_SOURCE[0])
+    with open(path, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    return PROP_TRAFFIC_BYTES if digest == PROP_TRAFFIC_SOURCE[1] else None
 
 
 def parse():
@@ -38,9 +51,14 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=48)
-    p.add_argument("--form", choices=["plain", "batch"], default="plain",
+    p.add_argument("--form", choices=["plain", "batch", "learned"], default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
-                        "persistent launch against one graph at a time")
+                        "persistent launch against one graph at a time; learned: the "
+                        "learned tail closure against plain TGT+ on BA-100k")
+    p.add_argument("--train-graphs", type=int, default=16, help="learned: training graphs")
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="plain: one untimed device-to-device copy of this many MB (a kernel "
+                        "of known traffic, to scale HBM counters)")
     p.add_argument("--replay", action="store_true", help="batch: replay a captured hipGraph")
     p.add_argument("--tune-json", default=None, help="batch: tuning table (written if absent)")
     return p.parse_args()
@@ -66,6 +84,7 @@ def cpu_baseline(graph, tau, tilde, nr, nsrc):
 
 
 BATCH_EPS = 1e-2
+TUNING = os.path.join(ROOT, "paper_2305_16086_amd", "tuning", "batch_fp32_mi355x.json")
 BATCH_MAX_L = 31
 LDS_PEAK_GBS = 128 * 256 * 2.4   # 128 B per clock per CU, 256 CUs, 2.4 GHz
 
@@ -93,7 +112,9 @@ def batch_form(a):
         return sc.sc_default_options(method=sc.SC_TGT, precision=0, max_L=BATCH_MAX_L,
                                      stream=stream.cuda_stream, **kw)
 
-    path = a.tune_json or os.path.join(tempfile.gettempdir(), "sc_batch_tuning.json")
+    path = a.tune_json or (TUNING if os.path.exists(TUNING)
+                           else os.path.join(tempfile.gettempdir(), "sc_batch_tuning.json"))
+    print(f"[batch] built {len(graphs)} graphs", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(), out=outs)   # lambda* of every graph
     torch.cuda.synchronize()
@@ -104,6 +125,7 @@ def batch_form(a):
     else:
         sc.sc_batch_autotune(b, BATCH_EPS, None, opts(), path)
     tune_s = time.perf_counter() - t0
+    print(f"[batch] tuning {path} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
     blocks = sc.sc_batch_blocks(b, opts())
     flags = sc.SC_GRAPH_REPLAY if a.replay else 0
     for _ in range(a.warmup):
@@ -116,6 +138,11 @@ def batch_form(a):
     dt = (time.perf_counter() - t0) / a.steps
     _, kst = sc.sc_batch_all_edges(b, BATCH_EPS, None, opts(flags=sc.SC_TIME_KERNELS), out=outs)
     res = [o.cpu().numpy() for o in outs]
+    print(f"[batch] timed {1e3 * dt:.1f} ms per step", file=sys.stderr, flush=True)
+    if a.no_cpu_baseline and a.steps <= 1:
+        # short profiling runs stop after the batched launches
+        print(json.dumps({"batch_ms_per_step": 1e3 * dt, "kernel_ms": kst["prop_ms"]}), flush=True)
+        return
 
     # one graph at a time, same accuracy target
     single = {}
@@ -216,6 +243,121 @@ def batch_form(a):
     print(json.dumps(line), flush=True)
 
 
+def learned_form(a):
+    """Learned tail closure (MLP 16-64-64-1, FP32 training on the GPU, BF16
+    inference) against plain TGT+ on the BA-100k graph at eps = 1e-3.
+    Training data: BA (m in {5, 10}) and G(n,p) (average degree 8, 10) graphs
+    with n log-uniform in [1e4, 1e5], seeds 100.., targets from TGT at L = 201
+    (untimed).  Both methods are timed on the same resident graph; accuracy on
+    the 2048 sampled edges whose exact SC the oracle stored."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    rng = np.random.default_rng(100)
+    t0 = time.perf_counter()
+    Xs, zs, ws = [], [], []
+    train_sizes = []
+    for k in range(a.train_graphs):
+        n = int(round(10 ** rng.uniform(4.0, 5.0)))
+        seed = 100 + k
+        if k % 2 == 0:
+            graph = gg.barabasi_albert(n, 5 if k % 4 == 0 else 10, seed)
+        else:
+            graph = gg.gnp_connected(n, 8.0 if k % 4 == 1 else 10.0, seed)
+        n, u, v = graph
+        g = sc.sc_build_graph(n, u, v)
+        m = len(u)
+        X = torch.empty(m * 16, dtype=torch.float32, device=dev)
+        z = torch.empty(m, dtype=torch.float32, device=dev)
+        w = torch.empty(m, dtype=torch.float32, device=dev)
+        sc.sc_closure_dataset(g, 201, 0, X, z, w)
+        torch.cuda.synchronize()
+        g.free()
+        Xs.append(X)
+        zs.append(z)
+        ws.append(w)
+        train_sizes.append((n, m))
+        print(f"[learned] dataset {k}: n={n} m={m} {time.perf_counter() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+    data_s = time.perf_counter() - t0
+    X = torch.cat(Xs)
+    z = torch.cat(zs)
+    w = torch.cat(ws)
+    del Xs, zs, ws
+    net = sc.sc_mlp_create(7)
+    t0 = time.perf_counter()
+    losses = sc.sc_mlp_train(net, X, z, w, sc.sc_default_train_options(epochs=30, batch=4096))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, z, w
+
+    graph = gg.workload("ba_100k", SEED)
+    n, u, v = graph
+    m = len(u)
+    g = sc.sc_build_graph(n, u, v)
+    out = torch.empty(m, dtype=torch.float64, device=dev)
+    gz = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
+
+    def run(method, **kw):
+        o = sc.sc_default_options(method=method, precision=0, block=BLOCK,
+                                  stream=stream.cuda_stream, **kw)
+        return sc.sc_all_edges_ex(g, EPS, 0, o, out=out)[1]
+
+    def run_eps(method, eps, **kw):
+        o = sc.sc_default_options(method=method, precision=0, block=BLOCK,
+                                  stream=stream.cuda_stream, **kw)
+        return sc.sc_all_edges_ex(g, eps, 0, o, out=out)[1]
+
+    res = {}
+    for name, method, eps, kw in (("learned", sc.SC_LEARNED, EPS, {"mlp": net.handle.value}),
+                                  ("tgt_plus", sc.SC_TGT_PLUS, EPS, {}),
+                                  ("tgt", sc.SC_TGT, EPS, {}),
+                                  ("tgt_eps_1e-5", sc.SC_TGT, 1e-5, {})):
+        for _ in range(a.warmup):
+            run_eps(method, eps, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            st = run_eps(method, eps, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        vals = out.cpu().numpy()
+        err = float(np.abs(vals[gz["edge_ids"]] - gz["sc"]).max()) if gz is not None else None
+        res[name] = {"edges_per_s": m / dt, "ms": 1e3 * dt, "max_abs_err_sampled": err,
+                     "fallback_edges": st["fallback_edges"], "L_used": st["L_used"]}
+    line = {
+        "metric": METRIC,
+        "value": res["learned"]["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res["learned"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"ba_100k: Barabasi-Albert n=100000, 10 edges per new node, seed 1 "
+                        f"(m={m}); learned tail closure (L0=8, MLP 16-64-64-1, BF16 inference, "
+                        f"certified fallback to TGT), eps=1e-3, FP32 propagation",
+            "learned": res["learned"], "plain_tgt_plus": res["tgt_plus"], "plain_tgt": res["tgt"],
+            "plain_tgt_eps_1e-5": res["tgt_eps_1e-5"],
+            "train": {"graphs": train_sizes, "samples": int(sum(mm for _, mm in train_sizes)),
+                      "dataset_s": data_s, "train_s": train_s,
+                      "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
+        },
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -223,6 +365,9 @@ def main():
         sys.exit(2)
     if a.form == "batch":
         batch_form(a)
+        return
+    if a.form == "learned":
+        learned_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc
@@ -242,6 +387,14 @@ def main():
                                   flags=flags, stream=stream.cuda_stream)
         kw = traces or {}
         return sc.sc_all_edges_ex(g, EPS, 0, o, out=out, **kw)[1]
+
+    if a.copy_probe_mb > 0:
+        # a fill (writes S bytes) and an elementwise product (reads S, writes S)
+        src = torch.ones(a.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(a.warmup):
         step()
@@ -311,7 +464,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_us": avg_launch_us,
             "launches": launches,
             "alg_bytes_per_launch": bytes_per_launch,

@@ -551,12 +551,18 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 }
 
 template <typename T>
-hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                            const AccJob& acc, hipStream_t st) {
+hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
+                                 const AccJob& acc, hipStream_t st) {
   const RowArgs<T> a = row_args<T>(g, B, partials, acc);
   const int blocks = a.row_blocks + acc_blocks(acc);
   SC_DISPATCH_B(B, (k_propagate<T, kB><<<blocks, kThreads, 0, st>>>(a, Yp, Yn)));
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
+                            const AccJob& acc, hipStream_t st) {
+  const hipError_t e = launch_propagate_rows<T>(g, B, Yp, Yn, partials, acc, st);
   if (e != hipSuccess) return e;
   return launch_fixup<T>(g, B, partials, Yn, st);
 }
@@ -609,6 +615,12 @@ template hipError_t launch_twohop<float>(const DeviceGraph&, int, const unsigned
                                          const unsigned*, float*, float*, hipStream_t);
 template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigned long long*,
                                           const unsigned*, double*, double*, hipStream_t);
+template hipError_t launch_propagate_rows<float>(const DeviceGraph&, int, const float*, float*,
+                                                float*, const AccJob&, hipStream_t);
+template hipError_t launch_propagate_rows<double>(const DeviceGraph&, int, const double*, double*,
+                                                 double*, const AccJob&, hipStream_t);
+template hipError_t launch_fixup<float>(const DeviceGraph&, int, const float*, float*, hipStream_t);
+template hipError_t launch_fixup<double>(const DeviceGraph&, int, const double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,
                                             float*, const AccJob&, hipStream_t);
 template hipError_t launch_propagate<double>(const DeviceGraph&, int, const double*, double*,

@@ -249,8 +249,10 @@ struct Runner {
         if (rc) return rc;
         HIP_TRY(hipEventRecord(a, st));
       }
-      HIP_TRY(launch_propagate<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st));
+      // the events bracket the row gathers alone (the kernel the roofline is taken on)
+      HIP_TRY(launch_propagate_rows<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st));
       if (timing) HIP_TRY(hipEventRecord(b, st));
+      HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
       ++stats.prop_launches;
       stats.prop_bytes += step_bytes();
       cur = 1 - cur;

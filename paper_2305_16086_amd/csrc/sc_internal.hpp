@@ -145,6 +145,14 @@ template <typename T>
 hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
                          const unsigned* anymask, T* Y, T* partials, hipStream_t st);
 
+// The two launches of launch_propagate, separately: the row gathers (giant
+// rows leave chunk sums in partials) and the giant-row fix-up.
+template <typename T>
+hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
+                                 const AccJob& acc, hipStream_t st);
+template <typename T>
+hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
+
 // Yn = P Yp (dense block gather); `acc` (may be empty) accumulates the step in Yp.
 template <typename T>
 hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
