@@ -70,3 +70,20 @@ def test_validation_of_even_cycle_plus_chord_is_not_bipartite_error():
         sc.sc_build_graph(n, u, v)
     except sc.ScError as e:       # without a GPU the device upload fails after validation
         assert e.code in (sc.SC_EHIP, sc.SC_ENOMEM)
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    """A shared library links with undefined symbols; every symbol of the
+    library's own namespace must be defined in it."""
+    import shutil
+    import subprocess
+    from paper_2305_16086_amd import sc
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    res = subprocess.run([nm, "-D", "--undefined-only", sc.LIB_PATH], capture_output=True,
+                         text=True, check=True)
+    missing = [ln.split()[-1] for ln in res.stdout.splitlines()
+               if ln.split() and (ln.split()[-1].startswith("_ZN2sc") or
+                                  ln.split()[-1].startswith("sc_"))]
+    assert not missing, missing
