@@ -15,6 +15,7 @@ namespace sc {
 namespace {
 
 constexpr int kThreads = 64 * kWavesPerBlock;
+constexpr int kWalkBlocks = 2048;   // persistent grid of the flattened walks
 
 inline unsigned grid_for(int64_t items, int per_block) {
   return static_cast<unsigned>((items + per_block - 1) / per_block);
@@ -465,7 +466,9 @@ __global__ __launch_bounds__(kThreads) void k_walks(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ slot_row, const int32_t* __restrict__ deg,
     const double* __restrict__ inv_deg, const T* __restrict__ Y, const int32_t* __restrict__ tau,
-    const long long* __restrict__ nr, double* __restrict__ gacc) {
+    const long long* __restrict__ nr, const long long* __restrict__ ctl,
+    double* __restrict__ gacc) {
+  if (ctl != nullptr && ctl[1] != 0) return;   // the flattened kernels took this block
   const int lane = threadIdx.x & 63;
   const int k = kbeg + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (k >= kend) return;
@@ -500,6 +503,148 @@ __global__ __launch_bounds__(kThreads) void k_walks(
   }
   acc = wave_sum(acc);
   if (lane == 0) gacc[k] += acc / static_cast<double>(n_r);
+}
+
+// ---------------------------------------------------------------- flattened walks
+// The walk pairs of a block's half-edges are cut into chunks of 64 pairs
+// (chunk_off: exclusive prefix of ceil(n_r / 64) over the block's slots, one
+// workgroup); waves take contiguous ranges of chunks, one pair per lane, and
+// store each chunk's sum (fixed butterfly); a last pass adds a slot's chunk
+// sums in chunk order.  ctl[0] = number of chunks, ctl[1] = 1 when they fit
+// the partial-sum buffer (else the per-slot kernel runs instead).
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+
+__global__ __launch_bounds__(kScanThreads) void k_walk_scan(int kbeg, int kend,
+                                                            const long long* __restrict__ nr,
+                                                            long long* __restrict__ chunk_off,
+                                                            long long capacity,
+                                                            long long* __restrict__ ctl) {
+  __shared__ long long wsum[kScanThreads / 64];
+  __shared__ long long carry_s;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nk = kend - kbeg;
+  if (tid == 0) carry_s = 0;
+  __syncthreads();
+  for (int base = 0; base < nk; base += kScanThreads * kScanPer) {
+    long long v[kScanPer];
+    long long tsum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      const int i = base + tid * kScanPer + q;
+      const long long r = i < nk ? nr[kbeg + i] : 0;
+      v[q] = r > 0 ? (r + 63) / 64 : 0;
+      tsum += v[q];
+    }
+    // inclusive scan of the thread sums inside the wave
+    long long x = tsum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    long long wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    long long run = carry_s + wpre + x - tsum;   // exclusive prefix of this thread
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      const int i = base + tid * kScanPer + q;
+      if (i < nk) chunk_off[i] = run;
+      run += v[q];
+    }
+    __syncthreads();
+    if (tid == kScanThreads - 1) carry_s = run;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    chunk_off[nk] = carry_s;
+    ctl[0] = carry_s;
+    ctl[1] = carry_s <= capacity ? 1 : 0;
+  }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_walks_flat(
+    int kbeg, int kend, int s0, int tilde, unsigned k0, unsigned k1,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ slot_row, const double* __restrict__ inv_deg,
+    const T* __restrict__ Y, const int32_t* __restrict__ tau, const long long* __restrict__ nr,
+    const long long* __restrict__ chunk_off, const long long* __restrict__ ctl,
+    double* __restrict__ part) {
+  if (ctl[1] == 0) return;
+  const long long total = ctl[0];
+  const int lane = threadIdx.x & 63;
+  const long long nwaves = static_cast<long long>(gridDim.x) * kWavesPerBlock;
+  const long long w = static_cast<long long>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+  const long long per = (total + nwaves - 1) / nwaves;
+  const long long c0 = w * per;
+  const long long c1 = min(total, c0 + per);
+  if (c0 >= c1) return;
+  const int nk = kend - kbeg;
+  // slot of chunk c0: the last i with chunk_off[i] <= c0 (and a chunk of its own)
+  int lo = 0, hi = nk;   // chunk_off[lo] <= c0 < chunk_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= c0) lo = mid;
+    else hi = mid;
+  }
+  int i = lo;
+  long long next = chunk_off[i + 1];
+  for (long long c = c0; c < c1; ++c) {
+    while (c >= next) {   // move to the slot that owns chunk c (skips slots without walks)
+      ++i;
+      next = chunk_off[i + 1];
+    }
+    const int k = kbeg + i;
+    const long long n_r = nr[k];
+    const long long r = (c - chunk_off[i]) * 64 + lane;
+    double x = 0.0;
+    if (r < n_r) {
+      const int len = tau[k] - tilde;
+      const int s = slot_row[k];
+      const int cc = s - s0;
+      const int j = col[k];
+      int pos0 = s, pos1 = j;
+      double sum0 = 0.0, sum1 = 0.0;
+      U32x4 w0, w1;
+      for (int t = 0; t < len; ++t) {
+        if ((t & 3) == 0) {
+          const uint32_t h = static_cast<uint32_t>(t >> 2);
+          w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                             static_cast<uint32_t>(r), h, k0, k1);
+          w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                             static_cast<uint32_t>(r), (1u << 31) | h, k0, k1);
+        }
+        const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
+        const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
+        pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[t & 3], static_cast<uint32_t>(e0 - b0)))];
+        pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[t & 3], static_cast<uint32_t>(e1 - b1)))];
+        sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + cc]);
+        sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + cc]);
+      }
+      x = (sum0 - sum1) * inv_deg[s];   // X of Eq. 11
+    }
+    x = wave_sum(x);
+    if (lane == 0) part[c] = x;
+  }
+}
+
+__global__ void k_walk_finish(int kbeg, int kend, const long long* __restrict__ nr,
+                              const long long* __restrict__ chunk_off,
+                              const long long* __restrict__ ctl, const double* __restrict__ part,
+                              double* __restrict__ gacc) {
+  if (ctl[1] == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kend - kbeg) return;
+  const long long n_r = nr[kbeg + i];
+  if (n_r <= 0) return;
+  double acc = 0.0;
+  for (long long c = chunk_off[i]; c < chunk_off[i + 1]; ++c) acc += part[c];
+  gacc[kbeg + i] += acc / static_cast<double>(n_r);
 }
 
 }  // namespace
@@ -579,14 +724,33 @@ hipError_t launch_work_totals(int kbeg, int kend, int tilde, const int32_t* tau_
 template <typename T>
 hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                         uint64_t seed, const T* Y, const int32_t* tau_slot,
-                        const int64_t* nr_slot, double* gacc, hipStream_t st) {
+                        const int64_t* nr_slot, double* gacc, const WalkScratch& ws,
+                        hipStream_t st) {
   if (kend <= kbeg) return hipSuccess;
   const unsigned k0 = static_cast<unsigned>(seed & 0xFFFFFFFFull);
   const unsigned k1 = static_cast<unsigned>(seed >> 32);
+  const long long* nr = reinterpret_cast<const long long*>(nr_slot);
+  long long* off = reinterpret_cast<long long*>(ws.chunk_off);
+  long long* ctl = reinterpret_cast<long long*>(ws.ctl);
+  const bool flat = ws.chunk_off && ws.part && ws.ctl;
+  if (flat) {
+    k_walk_scan<<<1, kScanThreads, 0, st>>>(kbeg, kend, nr, off, ws.capacity, ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SC_DISPATCH_B(B, (k_walks_flat<T, kB><<<kWalkBlocks, kThreads, 0, st>>>(
+                          kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row,
+                          g.inv_deg_d, Y, tau_slot, nr, off, ctl, ws.part)));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_walk_finish<<<grid_for(kend - kbeg, 256), 256, 0, st>>>(kbeg, kend, nr, off, ctl, ws.part,
+                                                             gacc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // per-slot kernel: the whole job without scratch, or blocks whose chunks do not fit
   SC_DISPATCH_B(B, (k_walks<T, kB><<<grid_for(kend - kbeg, kWavesPerBlock), kThreads, 0, st>>>(
                         kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row, g.deg,
-                        g.inv_deg_d, Y, tau_slot, reinterpret_cast<const long long*>(nr_slot),
-                        gacc)));
+                        g.inv_deg_d, Y, tau_slot, nr, flat ? ctl : nullptr, gacc)));
   return hipGetLastError();
 }
 
@@ -602,9 +766,9 @@ template hipError_t launch_walk_counts<double>(const DeviceGraph&, int, int, int
                                                const int32_t*, int64_t*, hipStream_t);
 template hipError_t launch_walks<float>(const DeviceGraph&, int, int, int, int, int, uint64_t,
                                         const float*, const int32_t*, const int64_t*, double*,
-                                        hipStream_t);
+                                        const WalkScratch&, hipStream_t);
 template hipError_t launch_walks<double>(const DeviceGraph&, int, int, int, int, int, uint64_t,
                                          const double*, const int32_t*, const int64_t*, double*,
-                                         hipStream_t);
+                                         const WalkScratch&, hipStream_t);
 
 }  // namespace sc

@@ -70,6 +70,10 @@ void sc_graph::release() {
   colscratch = nullptr;
   dev_free(work);
   dev_free(plan_work);
+  dev_free(walk.chunk_off);
+  dev_free(walk.part);
+  dev_free(walk.ctl);
+  walk.capacity = 0;
   dev_free(out_dev);
   dev_free(tau_out_dev);
   dev_free(nr_out_dev);
@@ -575,6 +579,12 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
   if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
   if (!g->plan_work) HIP_TRY(dev_alloc(&g->plan_work, 2 * 64));
+  if (!g->walk.chunk_off) {
+    HIP_TRY(dev_alloc(&g->walk.chunk_off, S + 1));
+    HIP_TRY(dev_alloc(&g->walk.ctl, 2));
+    g->walk.capacity = int64_t(1) << 22;   // chunk sums of up to 2^28 walk pairs per block
+    HIP_TRY(dev_alloc(&g->walk.part, g->walk.capacity));
+  }
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
   return SC_OK;
 }
@@ -778,7 +788,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
                                         R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, sb));
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
-                                  g->tau_slot, g->nr_slot, g->gacc, sb));
+                                  g->tau_slot, g->nr_slot, g->gacc, g->walk, sb));
     }
     HIP_TRY(hipEventRecord(g->pipe_ev[3 + pair], sb));
     R.st = st;

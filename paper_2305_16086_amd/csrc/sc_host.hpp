@@ -63,6 +63,7 @@ struct sc_graph {
   void* colscratch = nullptr;  // sc::kColScratchBytes
   unsigned long long* work = nullptr;
   unsigned long long* plan_work = nullptr;   // [2 x 64] walk totals per candidate switch step
+  sc::WalkScratch walk;                      // flattened walks (chunk offsets, chunk sums)
   // cached switch-step plan (the cost model depends only on these inputs)
   struct PlanKey {
     double eps;

@@ -185,12 +185,20 @@ hipError_t launch_walk_counts(const DeviceGraph& g, int kbeg, int kend, int s0, 
 hipError_t launch_work_totals(int kbeg, int kend, int tilde, const int32_t* tau_slot,
                               const int64_t* nr_slot, unsigned long long* work, hipStream_t st);
 
+// Scratch of the flattened walks (all null: one wave per half-edge instead).
+struct WalkScratch {
+  int64_t* chunk_off = nullptr;   // [slots of a block + 1]
+  double* part = nullptr;         // [capacity] chunk sums
+  int64_t capacity = 0;
+  int64_t* ctl = nullptr;         // [2]
+};
+
 // Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots.
 template <typename T>
 hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
-                        uint64_t seed,
-                        const T* Y, const int32_t* tau_slot, const int64_t* nr_slot,
-                        double* gacc, hipStream_t st);
+                        uint64_t seed, const T* Y, const int32_t* tau_slot,
+                        const int64_t* nr_slot, double* gacc, const WalkScratch& ws,
+                        hipStream_t st);
 
 // out[e] = gacc[slot(u_e->v_e)] + gacc[slot(v_e->u_e)] (Algorithm 2 line 12).
 hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,
