@@ -579,12 +579,6 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
   if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
   if (!g->plan_work) HIP_TRY(dev_alloc(&g->plan_work, 2 * 64));
-  if (!g->walk.chunk_off) {
-    HIP_TRY(dev_alloc(&g->walk.chunk_off, S + 1));
-    HIP_TRY(dev_alloc(&g->walk.ctl, 2));
-    g->walk.capacity = int64_t(1) << 22;   // chunk sums of up to 2^28 walk pairs per block
-    HIP_TRY(dev_alloc(&g->walk.part, g->walk.capacity));
-  }
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
   return SC_OK;
 }
@@ -686,6 +680,17 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   int tilde = Lmax;
   double coef = 0.0;
   const int64_t nr_cap = (1ll << 31) - 1;
+  if (plus && !g->walk.chunk_off) {
+    // flattened walks: chunk offsets per slot, chunk sums (a block whose chunks
+    // do not fit runs the per-slot kernel instead)
+    const int64_t S = g->rowptr_h[n];
+    HIP_TRY(sc::dev_alloc(&g->walk.chunk_off, S + 1));
+    HIP_TRY(sc::dev_alloc(&g->walk.ctl, 2));
+    g->walk.capacity = std::min<int64_t>(int64_t(1) << 22, 4 * S + 65536);
+    if (const char* cap = std::getenv("SC_WALK_CHUNK_CAPACITY"))   // smaller buffer (tests)
+      g->walk.capacity = std::max<int64_t>(1, std::min<int64_t>(g->walk.capacity, std::atoll(cap)));
+    HIP_TRY(sc::dev_alloc(&g->walk.part, g->walk.capacity));
+  }
   if (plus) {
     const double delta = o.delta > 0.0 ? o.delta : 1.0 / static_cast<double>(n);
     // Eq. 13 constant; m counts distinct edges

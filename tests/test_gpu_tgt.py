@@ -161,6 +161,23 @@ def test_tgt_plus_replay_parity(sc, precision, tilde, gamma):
         assert abs(int(nr[h]) - want[h]) <= max(1, 1e-5 * want[h]), (h, nr[h], want[h])
 
 
+def test_tgt_plus_walks_without_chunk_buffer_match(sc, monkeypatch):
+    """Blocks whose walk chunks do not fit the chunk-sum buffer run the per-slot
+    walk kernel: same walks, other summation order."""
+    graph = gg.barabasi_albert(300, 3, 4)
+    n, u, v = graph
+    kw = dict(method=sc.SC_TGT_PLUS, precision=1, tilde_tau=2, gamma=10, seed=777)
+    flat, st1, tau, tt, nr = run(sc, graph, 0.2, 7, **kw)
+    monkeypatch.setenv("SC_WALK_CHUNK_CAPACITY", "1")
+    slot, st2, tau2, tt2, nr2 = run(sc, graph, 0.2, 7, **kw)
+    np.testing.assert_array_equal(nr, nr2)
+    np.testing.assert_allclose(slot, flat, atol=1e-12, rtol=0)
+    G = otgt.Graph(n, u, v)
+    m = len(u)
+    _, _, ref = otgt.tgt_plus_replay(G, tau, tt, nr[:m], nr[m:], seed=777)
+    np.testing.assert_allclose(slot, ref, atol=FP64_TOL, rtol=0)
+
+
 def test_tgt_plus_auto_meets_eps_on_tree_gnp_1k(sc):
     graph = gg.workload("tree_gnp_1k", 2)
     eps = 1e-2
