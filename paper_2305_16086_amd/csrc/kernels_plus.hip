@@ -512,8 +512,8 @@ __global__ __launch_bounds__(kThreads) void k_walks(
 // store each chunk's sum (fixed butterfly); a last pass adds a slot's chunk
 // sums in chunk order.  ctl[0] = number of chunks, ctl[1] = 1 when they fit
 // the partial-sum buffer (else the per-slot kernel runs instead).
-constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 4;
+constexpr int kScanThreads = 256;   // one small workgroup: schedules beside the traversal kernels
+constexpr int kScanPer = 8;
 
 __global__ __launch_bounds__(kScanThreads) void k_walk_scan(int kbeg, int kend,
                                                             const long long* __restrict__ nr,

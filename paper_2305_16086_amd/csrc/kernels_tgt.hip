@@ -127,6 +127,9 @@ struct RowArgs {
   const int32_t* slot_row;
   const double* inv_deg_d;
   AccJob acc;
+  // rows known to be zero in Yp (nz[u] == 0) are read from the zero row n
+  const uint8_t* nz;
+  int n;
 };
 
 // gacc[k] += (Y[s][c] - Y[j][c]) / d_s for slot k = (s -> j), l <= tau_k (Eq. 9)
@@ -152,7 +155,8 @@ __device__ inline T gather_pieces(const RowArgs<T>& a, const T* __restrict__ Yp,
   T acc = T(0);
   for (int base = beg + 64 * first; base < end; base += 64 * step) {
     const int cnt = min(64, end - base);
-    const int myu = lane < cnt ? a.col[base + lane] : 0;
+    int myu = lane < cnt ? a.col[base + lane] : 0;
+    if (a.nz && lane < cnt && !a.nz[myu]) myu = a.n;   // a zero row: read the zero row
     if (G == 1) {
       for (int jj = 0; jj < cnt; jj += kBatch) {
         T v[kBatch];
@@ -224,7 +228,8 @@ __device__ inline void gather_run(const RowArgs<T>& a, const T* __restrict__ Yp,
   constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;
   const int nrows = tk.part;
   const int cnt = tk.end - tk.beg;
-  const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
+  int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
+  if (a.nz && lane < cnt && !a.nz[myu]) myu = a.n;   // a zero row: read the zero row
   const int myend = lane < nrows ? a.rowptr[tk.row + lane + 1] - tk.beg : 0;
   const T myinv = lane < nrows ? a.inv_deg[tk.row + lane] : T(0);
   T acc = T(0);
@@ -257,7 +262,7 @@ __device__ inline void gather_run(const RowArgs<T>& a, const T* __restrict__ Yp,
 template <typename T, int B>
 __device__ inline void twohop_run(const RowArgs<T>& a, const unsigned long long* __restrict__ mask,
                                   const unsigned* __restrict__ anymask, const Task& tk, int lane,
-                                  T* __restrict__ Y) {
+                                  T* __restrict__ Y, uint8_t* __restrict__ nzw) {
   const int nrows = tk.part;
   const int cnt = tk.end - tk.beg;
   const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
@@ -281,6 +286,10 @@ __device__ inline void twohop_run(const RowArgs<T>& a, const unsigned long long*
     }
     if (l + 1 == bnd) {
       Y[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+      if (nzw) {
+        const bool any = __ballot(acc != T(0)) != 0ull;
+        if (lane == 0) nzw[tk.row + ri] = any ? 1 : 0;
+      }
       acc = T(0);
       ++ri;
       bnd = __builtin_amdgcn_readlane(myend, ri & 63);
@@ -312,7 +321,7 @@ template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
                                                      const unsigned long long* __restrict__ mask,
                                                      const unsigned* __restrict__ anymask,
-                                                     T* __restrict__ Y) {
+                                                     T* __restrict__ Y, uint8_t* __restrict__ nzw) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int c = lane % B;
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
   if (static_cast<int>(blockIdx.x) < a.nwg) {
     const Task tk = a.wg_tasks[blockIdx.x];
     const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, wave, kWavesPerBlock, lane, c, gq);
-    wg_finish<T, B>(a, tk, sum, wave, lane, Y);
+    wg_finish<T, B>(a, tk, sum, wave, lane, Y);   // heavy rows keep their flag (1)
     return;
   }
   const int t = (blockIdx.x - a.nwg) * kWavesPerBlock + wave;
@@ -328,11 +337,15 @@ __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
     if (t >= a.nptasks) return;
     const Task tk = a.ptasks[t];
     if (tk.end - tk.beg <= 64) {
-      twohop_run<T, B>(a, mask, anymask, tk, lane, Y);
+      twohop_run<T, B>(a, mask, anymask, tk, lane, Y, nzw);
       return;
     }
     const T sum = twohop_pieces<T, B>(a, mask, anymask, tk.beg, tk.end, 0, 1, lane, c, gq);
     Y[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
+    if (nzw) {
+      const bool any = __ballot(sum != T(0)) != 0ull;
+      if (lane == 0) nzw[tk.row] = any ? 1 : 0;
+    }
     return;
   }
   if (t >= a.ntasks) return;
@@ -524,6 +537,8 @@ RowArgs<T> row_args(const DeviceGraph& g, int B, T* partials, const AccJob& acc)
   a.slot_row = g.slot_row;
   a.inv_deg_d = g.inv_deg_d;
   a.acc = acc;
+  a.nz = nullptr;
+  a.n = g.n;
   return a;
 }
 
@@ -542,9 +557,10 @@ hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hi
 
 template <typename T>
 hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
-                         const unsigned* anymask, T* Y, T* partials, hipStream_t st) {
+                         const unsigned* anymask, T* Y, T* partials, uint8_t* nz, hipStream_t st) {
   const RowArgs<T> a = row_args<T>(g, B, partials, AccJob{});
-  SC_DISPATCH_B(B, (k_twohop<T, kB><<<a.row_blocks, kThreads, 0, st>>>(a, mask, anymask, Y)));
+  SC_DISPATCH_B(B, (k_twohop<T, kB><<<a.row_blocks, kThreads, 0, st>>>(a, mask, anymask, Y,
+                                                                        B == 64 ? nz : nullptr)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_fixup<T>(g, B, partials, Y, st);
@@ -552,8 +568,9 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                                 const AccJob& acc, hipStream_t st) {
-  const RowArgs<T> a = row_args<T>(g, B, partials, acc);
+                                 const AccJob& acc, hipStream_t st, const uint8_t* nz) {
+  RowArgs<T> a = row_args<T>(g, B, partials, acc);
+  a.nz = B == 64 ? nz : nullptr;
   const int blocks = a.row_blocks + acc_blocks(acc);
   SC_DISPATCH_B(B, (k_propagate<T, kB><<<blocks, kThreads, 0, st>>>(a, Yp, Yn)));
   return hipGetLastError();
@@ -562,7 +579,7 @@ hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn
 template <typename T>
 hipError_t launch_propagate(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
                             const AccJob& acc, hipStream_t st) {
-  const hipError_t e = launch_propagate_rows<T>(g, B, Yp, Yn, partials, acc, st);
+  const hipError_t e = launch_propagate_rows<T>(g, B, Yp, Yn, partials, acc, st, nullptr);
   if (e != hipSuccess) return e;
   return launch_fixup<T>(g, B, partials, Yn, st);
 }
@@ -612,13 +629,13 @@ hipError_t launch_multi_axpy(const double* V, int ncols, int64_t ld, const doubl
 }
 
 template hipError_t launch_twohop<float>(const DeviceGraph&, int, const unsigned long long*,
-                                         const unsigned*, float*, float*, hipStream_t);
+                                         const unsigned*, float*, float*, uint8_t*, hipStream_t);
 template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigned long long*,
-                                          const unsigned*, double*, double*, hipStream_t);
+                                          const unsigned*, double*, double*, uint8_t*, hipStream_t);
 template hipError_t launch_propagate_rows<float>(const DeviceGraph&, int, const float*, float*,
-                                                float*, const AccJob&, hipStream_t);
+                                                float*, const AccJob&, hipStream_t, const uint8_t*);
 template hipError_t launch_propagate_rows<double>(const DeviceGraph&, int, const double*, double*,
-                                                 double*, const AccJob&, hipStream_t);
+                                                 double*, const AccJob&, hipStream_t, const uint8_t*);
 template hipError_t launch_fixup<float>(const DeviceGraph&, int, const float*, float*, hipStream_t);
 template hipError_t launch_fixup<double>(const DeviceGraph&, int, const double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,

@@ -70,6 +70,7 @@ void sc_graph::release() {
   colscratch = nullptr;
   dev_free(work);
   dev_free(plan_work);
+  dev_free(nz);
   dev_free(walk.chunk_off);
   dev_free(walk.part);
   dev_free(walk.ctl);
@@ -553,8 +554,16 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
       g->Y[i] = nullptr;
     }
     g->ybytes = 0;
-    for (int i = 0; i < 4; ++i) HIP_TRY(hipMalloc(&g->Y[i], yb));
+    // n rows of state plus the zero row n (never written; 64 columns of 8 bytes)
+    for (int i = 0; i < 4; ++i) {
+      HIP_TRY(hipMalloc(&g->Y[i], yb + 64 * sizeof(double)));
+      HIP_TRY(hipMemset(static_cast<char*>(g->Y[i]) + yb, 0, 64 * sizeof(double)));
+    }
     g->ybytes = yb;
+  }
+  if (!g->nz) {
+    HIP_TRY(dev_alloc(&g->nz, n));
+    HIP_TRY(hipMemset(g->nz, 1, n));
   }
   const size_t pb = static_cast<size_t>(std::max(g->d.nparts, 1)) * B * tsize;
   if (pb > g->pbytes) {

@@ -51,6 +51,7 @@ struct sc_graph {
   void* partials = nullptr;
   size_t pbytes = 0;
   unsigned long long* mask = nullptr;   // 2 x n words (two alternating buffers)
+  uint8_t* nz = nullptr;                // [n] nonzero rows of the two-hop state (1: unknown)
   unsigned* anymask = nullptr;          // 2 x ceil(n/32) words, one bit per node
   int mask_pending_s0 = -1;             // block whose bits are still set
   int mask_pending_buf = 0;
@@ -227,7 +228,7 @@ struct Runner {
     unsigned long long* mk = g->mask + static_cast<size_t>(buf) * g->d.n;
     unsigned* am = g->anymask + static_cast<size_t>(buf) * ((g->d.n + 31) / 32);
     cur = 0;
-    HIP_TRY(launch_twohop<T>(g->d, B, mk, am, Yb(cur), parts(), st));
+    HIP_TRY(launch_twohop<T>(g->d, B, mk, am, Yb(cur), parts(), g->nz, st));
     auto job = [&](int ell) {
       AccJob j;
       if (acc) {
@@ -251,7 +252,8 @@ struct Runner {
         HIP_TRY(hipEventRecord(a, st));
       }
       // the events bracket the row gathers alone (the kernel the roofline is taken on)
-      HIP_TRY(launch_propagate_rows<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st));
+      HIP_TRY(launch_propagate_rows<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st,
+                                       ell == 3 ? g->nz : nullptr));
       if (timing) HIP_TRY(hipEventRecord(b, st));
       HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
       ++stats.prop_launches;

@@ -140,16 +140,20 @@ hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, i
 hipError_t launch_mask_update(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
                               unsigned long long* mask, unsigned* anymask, hipStream_t st);
 
-// Y2 = P P Y0 for the indicator block via the neighbour masks.
+// Y2 = P P Y0 for the indicator block via the neighbour masks.  With B = 64
+// and nz, nz[x] = (row x of Y2 has a nonzero) for rows of at most kChunk
+// neighbours (heavier rows are left as they are, 1).
 template <typename T>
 hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* mask,
-                         const unsigned* anymask, T* Y, T* partials, hipStream_t st);
+                         const unsigned* anymask, T* Y, T* partials, uint8_t* nz, hipStream_t st);
 
 // The two launches of launch_propagate, separately: the row gathers (giant
-// rows leave chunk sums in partials) and the giant-row fix-up.
+// rows leave chunk sums in partials) and the giant-row fix-up.  With B = 64
+// and nz, neighbours u with nz[u] == 0 are read from Yp's zero row n (Yp holds
+// n + 1 rows): adding an exact zero leaves every sum unchanged.
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                                 const AccJob& acc, hipStream_t st);
+                                 const AccJob& acc, hipStream_t st, const uint8_t* nz = nullptr);
 template <typename T>
 hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
 
