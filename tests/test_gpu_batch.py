@@ -184,6 +184,23 @@ def test_batch_autotune_roundtrip(sc, tmp_path):
     b2.free()
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_batch_tiny_graphs(sc, precision):
+    # fewer nodes than one block, one row group, triangles and bridges
+    graphs = [gg.triangle_pendant(), gg.two_triangles_bridge(), gg.complete_graph(5),
+              gg.petersen_graph(), gg.cycle_graph(7)]
+    print(f"[gpu] batch tiny graphs precision={precision}", flush=True)
+    b = sc.sc_build_batch(graphs)
+    for block in (0, 1, 64):
+        o = sc.sc_default_options(method=sc.SC_TGT, precision=precision, block=block)
+        outs, _ = sc.sc_batch_all_edges(b, 1e-3, [9, 9, 9, 9, 9], o)
+        for i, (n, u, v) in enumerate(graphs):
+            ref = ex.s_tau_eigen(n, u, v, 9)
+            np.testing.assert_allclose(outs[i], ref, atol=FP64_TOL if precision else FP32_TOL,
+                                       rtol=0)
+    b.free()
+
+
 def test_batch_errors(sc):
     graphs = small_mix()[:2]
     b = sc.sc_build_batch(graphs)
