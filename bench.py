@@ -32,8 +32,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
 # HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
 # scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
 # kernel source they were taken on (first 16 hex digits of its SHA-256)
-PROP_TRAFFIC_BYTES = 421435333
-PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "d1911d48cdf5a77d")
+PROP_TRAFFIC_BYTES = 301974742
+PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "17c87523726ae8e4")
 
 
 def measured_traffic():
@@ -410,9 +410,10 @@ def main():
     value = m / (dt / a.steps)
 
     launches = sum(s["prop_launches"] for s in stats)
+    timed = sum(s["prop_timed"] for s in stats)
     prop_ms = sum(s["prop_ms"] for s in stats)
     prop_bytes = sum(s["prop_bytes"] for s in stats)
-    avg_launch_us = 1e3 * prop_ms / max(launches, 1)
+    avg_launch_us = 1e3 * prop_ms / max(timed, 1)
     bytes_per_launch = prop_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_us * 1e-6) / 1e9 if launches else 0.0
 
@@ -467,6 +468,7 @@ def main():
             "traffic": measured_traffic(),
             "avg_launch_us": avg_launch_us,
             "launches": launches,
+            "timed_launches": timed,
             "alg_bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": cpu,

@@ -867,6 +867,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       tot += t;
     }
     R.stats.prop_ms = tot;
+    R.stats.prop_timed = static_cast<int64_t>(R.ev_used / 2);
   }
   if (st_user) *st_user = R.stats;
   return SC_OK;

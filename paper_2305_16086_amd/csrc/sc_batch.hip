@@ -555,6 +555,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     s.block = B0;
     for (double l : P.lam) s.lambda_star = std::max(s.lambda_star, l);
     s.prop_launches = static_cast<int64_t>(P.launches.size());
+    s.prop_timed = kb && ke ? s.prop_launches : 0;
     s.prop_ms = kms;
     float tms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&tms, t0, t1));

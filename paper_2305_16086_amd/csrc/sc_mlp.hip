@@ -411,6 +411,7 @@ int learned_t(sc_graph* g, double eps, const sc_options& o, double* out_user, sc
       tot += tt;
     }
     R.stats.prop_ms = tot;
+    R.stats.prop_timed = static_cast<int64_t>(R.ev_used / 2);
   }
   if (st_user) *st_user = R.stats;
   return SC_OK;

@@ -82,6 +82,7 @@ class ScStats(C.Structure):
         ("prop_bytes", C.c_double),
         ("total_ms", C.c_double),
         ("fallback_edges", C.c_int64),
+        ("prop_timed", C.c_int64),
     ]
 
     def as_dict(self):
