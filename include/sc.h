@@ -280,11 +280,13 @@ int sc_batch_blocks(const sc_batch* b, const sc_options* o, int32_t* blocks_host
 
 /*
  * Measure the persistent launch for each size bucket (floor(log2 n),
- * floor(log2 2m/n)) of the batch, on up to 8 of its largest graphs, for
+ * floor(log2 2m/n)) of the batch, on up to 8 of its largest graphs: first
  * every B in {1, ..., 64} whose state fits the LDS (B <= 8 in device slabs
- * otherwise); keep the fastest per bucket for o->precision and write the
- * table with all timings as JSON to json_path (NULL: keep it in the handle
- * only).  The computed values do not depend on the choice beyond rounding.
+ * otherwise) with the default workgroup size of its LDS class, then the
+ * workgroup sizes 256, 512 and 1024 threads for the fastest B (states in
+ * LDS); keep the fastest per bucket for o->precision and write the table with
+ * all timings as JSON to json_path (NULL: keep it in the handle only).  The
+ * computed values do not depend on the choice beyond rounding.
  */
 int sc_batch_autotune(sc_batch* b, double eps, const int32_t* L, const sc_options* o,
                       const char* json_path);

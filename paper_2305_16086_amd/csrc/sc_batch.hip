@@ -19,14 +19,18 @@ using sc::fail;
 namespace {
 
 constexpr int kClasses = 4;         // LDS <= budget/4, <= budget/2, <= budget, device slab
-constexpr int kLaunchMax = kClasses * 7;   // one persistent launch per (class, block width)
+constexpr int kThreadChoices = 3;   // workgroup sizes 256, 512, 1024
+constexpr int kLaunchMax = kClasses * 7 * kThreadChoices;   // launches per (class, B, threads)
 constexpr int kClassThreads[kClasses] = {256, 512, 1024, 256};
 constexpr size_t kStaticLds = 64;   // the kernel's own __shared__ words (rounded up)
 constexpr size_t kSlabCap = size_t(8) << 30;   // device memory for slab states
 
 struct TuneEntry {
   int lg_n, lg_d, precision, block;
+  int threads;   // workgroup size of the persistent launch, 0: the LDS class's default
 };
+
+int threads_index(int nt) { return nt == 1024 ? 2 : nt == 512 ? 1 : 0; }
 
 int lg_floor(double x) { return x < 1.0 ? 0 : static_cast<int>(std::floor(std::log2(x))); }
 
@@ -201,13 +205,17 @@ void bucket_of(const sc_batch* b, int gi, int* lg_n, int* lg_d) {
   *lg_d = lg_floor(static_cast<double>(g->d.nslots) / static_cast<double>(g->d.n));
 }
 
-int block_for(const sc_batch* b, int gi, const sc_options& o) {
+int block_for(const sc_batch* b, int gi, const sc_options& o, int* threads = nullptr) {
   const size_t tsize = o.precision == 1 ? sizeof(double) : sizeof(float);
+  if (threads) *threads = 0;
   if (o.block > 0) return o.block;
   int ln, ld;
   bucket_of(b, gi, &ln, &ld);
   for (const TuneEntry& e : b->tune)
-    if (e.lg_n == ln && e.lg_d == ld && e.precision == o.precision) return e.block;
+    if (e.lg_n == ln && e.lg_d == ld && e.precision == o.precision) {
+      if (threads) *threads = e.threads;
+      return e.block;
+    }
   return default_block(b, gi, tsize);
 }
 
@@ -219,9 +227,9 @@ int class_of(const sc_batch* b, int n, int B, size_t tsize) {
   return 3;
 }
 
-// One persistent launch: the items of one (LDS class, block width) pair.
+// One persistent launch: the items of one (LDS class, block width, workgroup size).
 struct Launch {
-  int cls, B;
+  int cls, B, nt;
   int off, count;     // items [off, off + count) of the plan
   size_t dyn;         // dynamic LDS bytes
   int grid;
@@ -234,6 +242,7 @@ struct Plan {
   std::vector<int> L;                  // odd L per graph of the subset (0 = automatic)
   std::vector<double> lam;             // lambda* per graph of the subset (automatic only)
   std::vector<int> block;              // B per graph of the subset
+  std::vector<int> threads;            // workgroup size per graph (0: class default)
   std::vector<sc::BatchItem> items;    // grouped by launch
   std::vector<Launch> launches;        // most expensive first
   int64_t slab_elems = 0;
@@ -243,7 +252,8 @@ struct Plan {
 
 template <typename T>
 int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
-             const std::vector<int>& subset, const std::vector<int>* blocks, Plan& P) {
+             const std::vector<int>& subset, const std::vector<int>* blocks,
+             const std::vector<int>* threads, Plan& P) {
   const size_t tsize = sizeof(T);
   P.graphs = subset;
   P.eps = eps;
@@ -253,15 +263,21 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   P.L.resize(ng);
   P.lam.assign(ng, 0.0);
   P.block.resize(ng);
+  P.threads.assign(ng, 0);
   std::vector<double> est(ng);
   for (size_t q = 0; q < ng; ++q) {
     const int gi = subset[q];
     sc_graph* g = b->graphs[gi];
     const int Lg = L ? L[gi] : 0;
     if (Lg < 0) return fail(SC_EINVAL, "L must be >= 0 for every graph");
-    const int B = blocks ? (*blocks)[q] : block_for(b, gi, o);
+    int nt = 0;
+    const int B = blocks ? (*blocks)[q] : block_for(b, gi, o, &nt);
+    if (threads) nt = (*threads)[q];
     if (!valid_block(B)) return fail(SC_EINVAL, "batch block must be 1, 2, 4, 8, 16, 32 or 64");
+    if (nt != 0 && nt != 256 && nt != 512 && nt != 1024)
+      return fail(SC_EINVAL, "batch workgroup size must be 256, 512 or 1024");
     P.block[q] = B;
+    P.threads[q] = nt;
     if (Lg > 0) {
       P.L[q] = (Lg % 2 == 1) ? Lg : Lg + 1;
       est[q] = P.L[q];
@@ -293,7 +309,10 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     const sc_graph* g = b->graphs[gi];
     const int n = g->d.n, B = P.block[q];
     const int cls = class_of(b, n, B, tsize);
-    const int key = cls * 7 + __builtin_ctz(static_cast<unsigned>(B));
+    // device slabs always use 256-thread workgroups
+    const int nt = cls == 3 ? 256 : (P.threads[q] > 0 ? P.threads[q] : kClassThreads[cls]);
+    const int key = (cls * 7 + __builtin_ctz(static_cast<unsigned>(B))) * kThreadChoices +
+                    threads_index(nt);
     const double cost = est[q] * (static_cast<double>(g->d.nslots) + n) * std::sqrt(double(B));
     for (int s0 = 0; s0 < n; s0 += B) cand.push_back({cost, key, sc::BatchItem{gi, s0}});
     key_cost[key] += cost * ((n + B - 1) / B);
@@ -318,8 +337,10 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   int off = 0;
   for (int k : order) {
     Launch l;
-    l.cls = k / 7;
-    l.B = 1 << (k % 7);
+    const int ti = k % kThreadChoices;
+    l.nt = ti == 2 ? 1024 : ti == 1 ? 512 : 256;
+    l.cls = (k / kThreadChoices) / 7;
+    l.B = 1 << ((k / kThreadChoices) % 7);
     l.off = off;
     l.count = 0;
     for (size_t i = off; i < cand.size() && cand[i].key == k; ++i) ++l.count;
@@ -327,7 +348,7 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     l.dyn = l.cls < 3 ? key_lds[k] : 0;
     l.cost = key_cost[k];
     // grid: resident workgroups (occupancy), at most one per item
-    const int nt = kClassThreads[l.cls];
+    const int nt = l.nt;
     const bool lds = l.cls < 3;
     const void* fn = sc::batch_kernel_ptr<T>(nt, lds, l.B);
     if (lds) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -426,7 +447,7 @@ int enqueue_run(sc_batch* b, const Plan& P, hipStream_t st, hipEvent_t kb, hipEv
   if (kb) HIP_TRY(hipEventRecord(kb, st));
   for (size_t li = 0; li < P.launches.size(); ++li) {
     const Launch& l = P.launches[li];
-    HIP_TRY(sc::launch_batch<T>(kClassThreads[l.cls], l.cls < 3, l.B, l.grid, l.dyn, b->d_graphs,
+    HIP_TRY(sc::launch_batch<T>(l.nt, l.cls < 3, l.B, l.grid, l.dyn, b->d_graphs,
                                 b->d_items + l.off, l.count, b->d_misc + li,
                                 static_cast<T*>(b->slabs), P.slab_elems, st));
   }
@@ -446,8 +467,8 @@ std::string run_key(const Plan& P, const sc_options& o, double* const* outs, boo
   for (size_t q = 0; q < P.graphs.size(); ++q) {
     uint64_t lb;
     std::memcpy(&lb, &P.lam[q], sizeof(lb));
-    std::snprintf(buf, sizeof(buf), "%d,%d,%d,%" PRIx64 ",%p;", P.graphs[q], P.L[q], P.block[q],
-                  lb, host_out ? nullptr : static_cast<void*>(outs[q]));
+    std::snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%" PRIx64 ",%p;", P.graphs[q], P.L[q], P.block[q],
+                  P.threads[q], lb, host_out ? nullptr : static_cast<void*>(outs[q]));
     k += buf;
   }
   return k;
@@ -455,14 +476,15 @@ std::string run_key(const Plan& P, const sc_options& o, double* const* outs, boo
 
 template <typename T>
 int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
-              const std::vector<int>& subset, const std::vector<int>* blocks, double* const* out,
+              const std::vector<int>& subset, const std::vector<int>* blocks,
+              const std::vector<int>* threads, double* const* out,
               sc_stats* st_user, float* kernel_ms) {
   hipStream_t st = static_cast<hipStream_t>(o.stream);
   const bool dev_ptrs = (o.flags & SC_DEVICE_PTRS) != 0;
   const bool replay = (o.flags & SC_GRAPH_REPLAY) != 0;
   const bool timing = (o.flags & SC_TIME_KERNELS) != 0 || kernel_ms != nullptr;
   Plan P;
-  int rc = plan_run<T>(b, eps, L, o, subset, blocks, P);
+  int rc = plan_run<T>(b, eps, L, o, subset, blocks, threads, P);
   if (rc) return rc;
   // device outputs per graph
   std::vector<double*> outs(P.graphs.size());
@@ -568,6 +590,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
 
 int run_dispatch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
                  const std::vector<int>& subset, const std::vector<int>* blocks,
+                 const std::vector<int>* threads,
                  double* const* out, sc_stats* st, float* kernel_ms) {
   if (!(eps > 0.0 && eps < 1.0)) return fail(SC_EINVAL, "eps must lie in (0, 1)");
   if (o.method != SC_TGT) return fail(SC_ENOTIMPL, "batches run TGT (method 0) only");
@@ -577,8 +600,9 @@ int run_dispatch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != b->device) return fail(SC_EINVAL, "current device differs from the batch's device");
-  return o.precision == 1 ? run_batch<double>(b, eps, L, o, subset, blocks, out, st, kernel_ms)
-                          : run_batch<float>(b, eps, L, o, subset, blocks, out, st, kernel_ms);
+  return o.precision == 1
+             ? run_batch<double>(b, eps, L, o, subset, blocks, threads, out, st, kernel_ms)
+             : run_batch<float>(b, eps, L, o, subset, blocks, threads, out, st, kernel_ms);
 }
 
 }  // namespace
@@ -703,7 +727,7 @@ extern "C" int sc_batch_all_edges(sc_batch* b, double eps, const int32_t* L,
     if (!out[gi]) return fail(SC_EINVAL, "NULL output pointer");
   std::vector<int> all(b->graphs.size());
   std::iota(all.begin(), all.end(), 0);
-  return run_dispatch(b, eps, L, *o, all, nullptr, out, st, nullptr);
+  return run_dispatch(b, eps, L, *o, all, nullptr, nullptr, out, st, nullptr);
 }
 
 // ---------------------------------------------------------------------- autotuner
@@ -744,31 +768,51 @@ extern "C" int sc_batch_autotune(sc_batch* b, double eps, const int32_t* L, cons
     for (int gi : k.graphs) outs[gi] = b->out_dev + b->edge_off[gi];
     int nmax = 0;
     for (int gi : k.graphs) nmax = std::max(nmax, b->graphs[gi]->d.n);
-    int best = -1;
+    int best = -1, best_nt = 0;
     float best_ms = 0.0f;
     std::string trials;
+    auto trial = [&](int B, int nt, float* ms) -> int {
+      std::vector<int> blocks(k.graphs.size(), B), threads(k.graphs.size(), nt);
+      int rc = run_dispatch(b, eps, L, so, k.graphs, &blocks, &threads, outs.data(), nullptr, ms);
+      if (rc) return rc;   // the first run warms up (lambda*, attributes, caches)
+      rc = run_dispatch(b, eps, L, so, k.graphs, &blocks, &threads, outs.data(), nullptr, ms);
+      if (rc) return rc;
+      char buf[64];
+      std::snprintf(buf, sizeof(buf), "%s{\"block\": %d, \"threads\": %d, \"ms\": %.4f}",
+                    trials.empty() ? "" : ", ", B, nt, *ms);
+      trials += buf;
+      return SC_OK;
+    };
+    // block width with the LDS class's workgroup size
     for (int B = 1; B <= 64; B <<= 1) {
       const bool fits = state_bytes(nmax, B, tsize) + kStaticLds <= b->lds_budget;
       if (!fits && B > 8) continue;   // device-slab states: narrow blocks only
-      std::vector<int> blocks(k.graphs.size(), B);
       float ms = 0.0f;
-      int rc = run_dispatch(b, eps, L, so, k.graphs, &blocks, outs.data(), nullptr, &ms);  // warm-up
+      const int rc = trial(B, 0, &ms);
       if (rc) return rc;
-      rc = run_dispatch(b, eps, L, so, k.graphs, &blocks, outs.data(), nullptr, &ms);
-      if (rc) return rc;
-      char buf[48];
-      std::snprintf(buf, sizeof(buf), "%s{\"block\": %d, \"ms\": %.4f}", trials.empty() ? "" : ", ", B, ms);
-      trials += buf;
       if (best < 0 || ms < best_ms) {
         best = B;
         best_ms = ms;
       }
     }
-    found.push_back({k.ln, k.ld, o->precision, best});
-    char head[160];
+    // then the workgroup size for that width (states in LDS only)
+    if (state_bytes(nmax, best, tsize) + kStaticLds <= b->lds_budget) {
+      for (int nt : {256, 512, 1024}) {
+        float ms = 0.0f;
+        const int rc = trial(best, nt, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+          best_nt = nt;
+          best_ms = ms;
+        }
+      }
+    }
+    found.push_back({k.ln, k.ld, o->precision, best, best_nt});
+    char head[192];
     std::snprintf(head, sizeof(head),
-                  "    {\"lg_n\": %d, \"lg_d\": %d, \"precision\": %d, \"block\": %d, \"graphs\": %zu, \"trials\": [",
-                  k.ln, k.ld, o->precision, best, k.graphs.size());
+                  "    {\"lg_n\": %d, \"lg_d\": %d, \"precision\": %d, \"block\": %d, \"threads\": %d, "
+                  "\"graphs\": %zu, \"trials\": [",
+                  k.ln, k.ld, o->precision, best, best_nt, k.graphs.size());
     json += head + trials + "]}" + (bi + 1 < buckets.size() ? ",\n" : "\n");
   }
   json += "  ]\n}\n";
@@ -805,6 +849,13 @@ extern "C" int sc_batch_load_tuning(sc_batch* b, const char* json_path) {
     if (std::sscanf(text.c_str() + pos, "{\"lg_n\": %d, \"lg_d\": %d, \"precision\": %d, \"block\": %d",
                     &e.lg_n, &e.lg_d, &e.precision, &e.block) != 4 ||
         !valid_block(e.block) || (e.precision != 0 && e.precision != 1))
+      return fail(SC_EINVAL, "malformed tuning entry");
+    // optional workgroup size (0 = the LDS class's default)
+    const size_t end = text.find('}', pos);
+    const size_t th = text.find("\"threads\":", pos);
+    if (th != std::string::npos && th < end &&
+        (std::sscanf(text.c_str() + th, "\"threads\": %d", &e.threads) != 1 ||
+         (e.threads != 0 && e.threads != 256 && e.threads != 512 && e.threads != 1024)))
       return fail(SC_EINVAL, "malformed tuning entry");
     found.push_back(e);
     ++pos;
