@@ -356,9 +356,11 @@ __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
 
 // ------------------------------------------------------------------ dense propagation
 // Workgroups [0, nwg): heavy rows and giant-row chunks; then wave tasks; then
-// the accumulation of the step held in Yp (fused, saves a launch).
+// the accumulation of the step held in Yp (fused, saves a launch).  Register
+// use is held to 6 waves per SIMD: more waves with shallower gather batches run
+// the kernel faster alone but slow the concurrent tail of the block pipeline.
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_propagate(RowArgs<T> a, const T* __restrict__ Yp,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_propagate(RowArgs<T> a, const T* __restrict__ Yp,
                                                         T* __restrict__ Yn) {
   if (static_cast<int>(blockIdx.x) >= a.row_blocks) {
     const int k = a.acc.kbeg + (blockIdx.x - a.row_blocks) * kThreads + threadIdx.x;
