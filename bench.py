@@ -32,8 +32,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
 # HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
 # scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
 # kernel source they were taken on (first 16 hex digits of its SHA-256)
-PROP_TRAFFIC_BYTES = 300955497
-PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "66da32182a5ba009")
+PROP_TRAFFIC_BYTES = 300910044
+PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "868a66b3e2f80d7e")
 
 
 def measured_traffic():

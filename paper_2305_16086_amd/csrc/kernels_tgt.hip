@@ -201,7 +201,10 @@ __device__ inline T twohop_pieces(const RowArgs<T>& a, const unsigned long long*
     if (G == 1) {
       const int mlo = static_cast<int>(mym & 0xFFFFFFFFull);
       const int mhi = static_cast<int>(mym >> 32);
-      for (int jj = 0; jj < cnt; ++jj) {
+      unsigned long long ph = __ballot(hit);   // only marked slots contribute, in slot order
+      while (ph) {
+        const int jj = __builtin_ctzll(ph);
+        ph &= ph - 1ull;
         const unsigned long long mk =
             (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readlane(mhi, jj))) << 32) |
             static_cast<unsigned>(__builtin_amdgcn_readlane(mlo, jj));
@@ -274,26 +277,29 @@ __device__ inline void twohop_run(const RowArgs<T>& a, const unsigned long long*
   const unsigned long long hits = __ballot(hit);
   const int mlo = static_cast<int>(mym & 0xFFFFFFFFull);
   const int mhi = static_cast<int>(mym >> 32);
-  T acc = T(0);
-  int ri = 0;
-  int bnd = __builtin_amdgcn_readlane(myend, 0);
-  for (int l = 0; l < cnt; ++l) {
-    if ((hits >> l) & 1ull) {
+  // row by row, visiting only the slots some column marks (in slot order, so
+  // the sums are those of the full slot loop: the other slots add nothing)
+  int rbeg = 0;
+  for (int ri = 0; ri < nrows; ++ri) {
+    const int rend = __builtin_amdgcn_readlane(myend, ri);
+    const unsigned long long below_end = rend >= 64 ? ~0ull : ((1ull << rend) - 1ull);
+    const unsigned long long below_beg = (1ull << rbeg) - 1ull;   // rbeg < 64
+    unsigned long long rh = hits & below_end & ~below_beg;
+    T acc = T(0);
+    while (rh) {
+      const int l = __builtin_ctzll(rh);
+      rh &= rh - 1ull;
       const unsigned long long mk =
           (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readlane(mhi, l))) << 32) |
           static_cast<unsigned>(__builtin_amdgcn_readlane(mlo, l));
       if ((mk >> lane) & 1ull) acc += bcast(myw, l);
     }
-    if (l + 1 == bnd) {
-      Y[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
-      if (nzw) {
-        const bool any = __ballot(acc != T(0)) != 0ull;
-        if (lane == 0) nzw[tk.row + ri] = any ? 1 : 0;
-      }
-      acc = T(0);
-      ++ri;
-      bnd = __builtin_amdgcn_readlane(myend, ri & 63);
+    Y[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+    if (nzw) {
+      const bool any = __ballot(acc != T(0)) != 0ull;
+      if (lane == 0) nzw[tk.row + ri] = any ? 1 : 0;
     }
+    rbeg = rend;
   }
 }
 
