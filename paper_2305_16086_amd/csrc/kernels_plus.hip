@@ -122,133 +122,6 @@ __global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part, i
   pmn[static_cast<size_t>(cc) * nparts + p0 + pl] = smn[pl * B + cc];
 }
 
-// one wave per column
-template <typename T, int B>
-__global__ __launch_bounds__(64) void k_colthresh(int gamma, int nparts, const T* __restrict__ pmx,
-                                                  const T* __restrict__ pmn, T* __restrict__ thr,
-                                                  int* __restrict__ nact, ColStats* __restrict__ cs) {
-  constexpr int kPer = kColParts / 64;
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  double v[kPer];
-  double mx = -DBL_MAX, mn = DBL_MAX;
-  double w[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {   // all loads issued before any use
-    const int p = lane + 64 * k;
-    const size_t o = static_cast<size_t>(c) * nparts + (p < nparts ? p : 0);
-    v[k] = p < nparts ? static_cast<double>(pmx[o]) : -1.0;
-    w[k] = p < nparts ? static_cast<double>(pmn[o]) : 2.0;
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    // empty chunks carry max -1 and min 2, outside [0, 1]
-    mx = fmax(mx, v[k]);
-    mn = fmin(mn, w[k]);
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, off, 64));
-    mn = fmin(mn, __shfl_xor(mn, off, 64));
-  }
-  // gamma rounds: remove the largest remaining chunk maximum
-  double theta = -1.0;
-  for (int r = 0; r < gamma; ++r) {
-    double best = -1.0;
-    int at = -1;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (v[k] > best) {
-        best = v[k];
-        at = k;
-      }
-    double wbest = best;
-    int wlane = lane;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(wbest, off, 64);
-      const int ol = __shfl_xor(wlane, off, 64);
-      if (ob > wbest || (ob == wbest && ol < wlane)) {
-        wbest = ob;
-        wlane = ol;
-      }
-    }
-    if (wbest < 0.0) {   // fewer than gamma non-empty chunks: keep every entry
-      theta = -1.0;
-      break;
-    }
-    theta = wbest;
-    if (lane == wlane) {
-#pragma unroll
-      for (int k = 0; k < kPer; ++k)
-        if (k == at) v[k] = -1.0;
-    }
-  }
-  if (lane == 0) {
-    thr[c] = static_cast<T>(theta);
-    nact[c] = 0;
-    cs[c].maxV = mx;
-    cs[c].minV = mn;
-  }
-}
-
-template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_colscan(int n, int rows_per_part, int gamma,
-                                                      const T* __restrict__ Y,
-                                                      const T* __restrict__ pmx,
-                                                      const T* __restrict__ thr,
-                                                      T* __restrict__ pv, int* __restrict__ pi,
-                                                      int* __restrict__ nact,
-                                                      int* __restrict__ act) {
-  constexpr int G = 64 / B;
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int c = lane % B;
-  const int part = wave * G + lane / B;
-  const size_t o = static_cast<size_t>(part) * B + c;
-  const T th = thr[c];
-  const T cmax = pmx[static_cast<size_t>(c) * kColParts + part];
-  const bool mine = cmax >= th && cmax >= T(0);
-  if (__ballot(mine) == 0ull) return;   // whole wave uniform
-  const int x0 = part * rows_per_part;
-  const int x1 = mine ? min(n, x0 + rows_per_part) : x0;
-  double lv[kMaxGamma];
-  int li[kMaxGamma];
-#pragma unroll
-  for (int p = 0; p < kMaxGamma; ++p) {
-    lv[p] = -DBL_MAX;
-    li[p] = INT_MAX;
-  }
-  double last = -DBL_MAX;
-  for (int xb = x0; xb < x1; xb += 8) {
-    T q[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      q[r] = (xb + r < x1) ? Y[static_cast<size_t>(xb + r) * B + c] : T(-1);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const double v = static_cast<double>(q[r]);
-      // ids increase along the scan: only a strictly larger value outranks the tail
-      if (xb + r < x1 && q[r] >= th && v > last) {
-        list_insert(lv, li, gamma, v, xb + r);
-        int dummy;
-        list_last(lv, li, gamma, &last, &dummy);
-      }
-    }
-  }
-  if (mine) {
-#pragma unroll
-    for (int p = 0; p < kMaxGamma; ++p) {
-      if (p < gamma) {
-        pv[o * gamma + p] = static_cast<T>(lv[p]);
-        pi[o * gamma + p] = li[p];
-      }
-    }
-    const int k = atomicAdd(&nact[c], 1);
-    act[static_cast<size_t>(c) * kColParts + k] = part;
-  }
-}
-
 __device__ inline void wave_best(double& v, int& id, int& owner) {
   // (value desc, id asc) arg-best over the wave, fixed butterfly
 #pragma unroll
@@ -263,6 +136,220 @@ __device__ inline void wave_best(double& v, int& id, int& owner) {
     }
   }
 }
+
+// Pass B: one workgroup of kThreshWaves waves per column.  Each wave takes
+// kColParts / kThreshWaves chunk maxima, keeps its gamma largest (with
+// multiplicity), and the first wave picks theta = the gamma-th largest of all
+// from those lists.  Then the chunks whose maximum reaches theta (and is not
+// empty) are listed in ascending chunk order: act[c*kColParts + k], nact[c].
+constexpr int kThreshWaves = 4;
+
+template <typename T, int B>
+__global__ __launch_bounds__(64 * kThreshWaves) void k_colthresh(
+    int gamma, int nparts, const T* __restrict__ pmx, const T* __restrict__ pmn,
+    T* __restrict__ thr, int* __restrict__ nact, int* __restrict__ act, ColStats* __restrict__ cs) {
+  constexpr int kPer = kColParts / (64 * kThreshWaves);
+  __shared__ double s_top[kThreshWaves][kMaxGamma];
+  __shared__ double s_mx[kThreshWaves], s_mn[kThreshWaves];
+  __shared__ double s_theta;
+  __shared__ int s_cnt[kThreshWaves];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double v[kPer];
+  double mx = -DBL_MAX, mn = DBL_MAX;
+  {
+    double w[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {   // all loads issued before any use
+      const int p = wave * (kPer * 64) + k * 64 + lane;
+      const size_t o = static_cast<size_t>(c) * nparts + (p < nparts ? p : 0);
+      v[k] = p < nparts ? static_cast<double>(pmx[o]) : -1.0;
+      w[k] = p < nparts ? static_cast<double>(pmn[o]) : 2.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      // empty chunks carry max -1 and min 2, outside [0, 1]
+      mx = fmax(mx, v[k]);
+      mn = fmin(mn, w[k]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+  }
+  // this wave's gamma largest chunk maxima
+  {
+    double r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) r[k] = v[k];
+    for (int q = 0; q < gamma; ++q) {
+      double best = -1.0;
+      int at = -1;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        if (r[k] > best) {
+          best = r[k];
+          at = k;
+        }
+      double wbest = best;
+      int wlane = lane;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(wbest, off, 64);
+        const int ol = __shfl_xor(wlane, off, 64);
+        if (ob > wbest || (ob == wbest && ol < wlane)) {
+          wbest = ob;
+          wlane = ol;
+        }
+      }
+      if (lane == 0) s_top[wave][q] = wbest;
+      if (lane == wlane) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+          if (k == at) r[k] = -1.0;
+      }
+    }
+  }
+  if (lane == 0) {
+    s_mx[wave] = mx;
+    s_mn[wave] = mn;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // theta over the kThreshWaves lists (lane = candidate)
+    double cand = -1.0;
+    if (lane < kThreshWaves * gamma) cand = s_top[lane / gamma][lane % gamma];
+    double theta = -1.0;
+    for (int q = 0; q < gamma; ++q) {
+      double wbest = cand;
+      int wlane = lane;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(wbest, off, 64);
+        const int ol = __shfl_xor(wlane, off, 64);
+        if (ob > wbest || (ob == wbest && ol < wlane)) {
+          wbest = ob;
+          wlane = ol;
+        }
+      }
+      if (wbest < 0.0) {   // fewer than gamma non-empty chunks: keep every entry
+        theta = -1.0;
+        break;
+      }
+      theta = wbest;
+      if (lane == wlane) cand = -1.0;
+    }
+    if (lane == 0) {
+      s_theta = theta;
+      double gmx = s_mx[0], gmn = s_mn[0];
+      for (int q = 1; q < kThreshWaves; ++q) {
+        gmx = fmax(gmx, s_mx[q]);
+        gmn = fmin(gmn, s_mn[q]);
+      }
+      thr[c] = static_cast<T>(theta);
+      cs[c].maxV = gmx;
+      cs[c].minV = gmn;
+    }
+  }
+  __syncthreads();
+  // active chunks in ascending order
+  const double theta = s_theta;
+  unsigned long long bal[kPer];
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const T tv = static_cast<T>(theta);
+    const bool on = v[k] >= 0.0 && static_cast<T>(v[k]) >= tv;
+    bal[k] = __ballot(on);
+    cnt += __popcll(bal[k]);
+  }
+  if (lane == 0) s_cnt[wave] = cnt;
+  __syncthreads();
+  int base = 0;
+  for (int q = 0; q < wave; ++q) base += s_cnt[q];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if ((bal[k] >> lane) & 1ull) {
+      const int idx = base + __popcll(bal[k] & ((1ull << lane) - 1ull));
+      act[static_cast<size_t>(c) * kColParts + idx] = wave * (kPer * 64) + k * 64 + lane;
+    }
+    base += __popcll(bal[k]);
+  }
+  if (threadIdx.x == 64 * kThreshWaves - 1) nact[c] = base;
+}
+
+// Pass C: kScanWaves waves per column walk the column's active chunks; for
+// each, the lanes take 64 rows at a time and the wave keeps the gamma best
+// entries (value desc, id asc) that reach theta, in lanes 0..gamma-1.
+constexpr int kScanWaves = 16;
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_colscan(int n, int rows_per_part, int gamma,
+                                                      const T* __restrict__ Y,
+                                                      const T* __restrict__ thr,
+                                                      T* __restrict__ pv, int* __restrict__ pi,
+                                                      const int* __restrict__ nact,
+                                                      const int* __restrict__ act) {
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int c = gw / kScanWaves;
+  const int wc = gw % kScanWaves;
+  const int na = nact[c];
+  const T th = thr[c];
+  for (int k = wc; k < na; k += kScanWaves) {
+    const int part = act[static_cast<size_t>(c) * kColParts + k];
+    const int x0 = part * rows_per_part;
+    const int x1 = min(n, x0 + rows_per_part);
+    double lv = -DBL_MAX;   // list entry r sits in lane r (r < gamma)
+    int li = INT_MAX;
+    for (int xb = x0; xb < x1; xb += 64) {
+      const int x = xb + lane;
+      double bv = -DBL_MAX;
+      int bi = INT_MAX;
+      if (x < x1) {
+        const T q = Y[static_cast<size_t>(x) * B + c];
+        if (q >= th) {
+          bv = static_cast<double>(q);
+          bi = x;
+        }
+      }
+      // new list = best gamma of (list, batch); each lane holds at most two entries
+      double nv = -DBL_MAX;
+      int ni = INT_MAX;
+      bool list_used = false, batch_used = false;
+      for (int r = 0; r < gamma; ++r) {
+        const bool take_list = !list_used && (batch_used || ranks_before(lv, li, bv, bi));
+        double cv = take_list ? lv : (batch_used ? -DBL_MAX : bv);
+        int ci = take_list ? li : (batch_used ? INT_MAX : bi);
+        if (list_used && batch_used) {
+          cv = -DBL_MAX;
+          ci = INT_MAX;
+        }
+        int owner = lane;
+        wave_best(cv, ci, owner);
+        if (ci == INT_MAX) break;   // no entries left
+        if (lane == r) {
+          nv = cv;
+          ni = ci;
+        }
+        if (lane == owner) {
+          if (take_list) list_used = true;
+          else batch_used = true;
+        }
+      }
+      lv = nv;
+      li = ni;
+    }
+    if (lane < gamma) {
+      const size_t o = static_cast<size_t>(part) * B + c;
+      pv[o * gamma + lane] = static_cast<T>(lv);
+      pi[o * gamma + lane] = li;
+    }
+  }
+}
+
 
 // one wave per column; the registered chunk order is arbitrary but the
 // selection uses the total order (value desc, id asc), so the result is not
@@ -682,13 +769,14 @@ hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const
                         g.n, rows, nparts, Y, pmx, pmn)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64, 0, st>>>(gamma, nparts, pmx, pmn, thr, nact,
-                                                              cs)));
+  SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64 * kThreshWaves, 0, st>>>(
+                        gamma, nparts, pmx, pmn, thr, nact, act, cs)));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (gamma > 0) {
-    SC_DISPATCH_B(B, (k_colscan<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(
-                          g.n, rows, gamma, Y, pmx, thr, pv, pi, nact, act)));
+    SC_DISPATCH_B(B, (k_colscan<T, kB><<<grid_for(static_cast<int64_t>(ncols) * kScanWaves,
+                                                  kWavesPerBlock), kThreads, 0, st>>>(
+                          g.n, rows, gamma, Y, thr, pv, pi, nact, act)));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
