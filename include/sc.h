@@ -53,7 +53,7 @@ enum {
 
 /* run flags (sc_options.flags) */
 #define SC_DEVICE_PTRS 0x1u  /* out / trace arrays are device pointers */
-#define SC_TIME_KERNELS 0x4u /* bracket propagation launches with HIP events (stats)  */
+#define SC_TIME_KERNELS 0x4u /* time a sample of propagation launches with HIP events */
 #define SC_GRAPH_REPLAY 0x8u /* sc_batch_all_edges: record the device work as a hipGraph
                                 on the first call, replay it on later identical calls */
 
@@ -96,13 +96,16 @@ typedef struct sc_stats {
   double lambda_star;      /* value used for automatic truncation (0 if not needed)   */
   int64_t walks;           /* walk pairs simulated                                    */
   int64_t walk_steps;      /* single-walk steps simulated                             */
-  int64_t prop_launches;   /* dense propagation launches                              */
+  int64_t prop_launches;   /* dense propagation launches that gather every neighbour
+                              row (at block width 64 the first dense step after the
+                              two-hop step skips zero rows and is not counted)      */
   double prop_ms;          /* sum of the timed propagation launches (SC_TIME_KERNELS) */
-  double prop_bytes;       /* algorithmic bytes of all propagation launches           */
+  double prop_bytes;       /* algorithmic bytes of the counted propagation launches   */
   double total_ms;         /* wall time of the call on the stream                     */
   int64_t fallback_edges;  /* SC_LEARNED: edges computed by the fallback traversal    */
-  int64_t prop_timed;      /* launches whose times prop_ms sums (SC_TIME_KERNELS
-                              brackets every 15th propagation launch)             */
+  int64_t prop_timed;      /* launches whose times prop_ms sums (SC_TIME_KERNELS times
+                              every 15th counted launch with events that take the
+                              kernel's own start and end)                          */
 } sc_stats;
 
 /* Fill *o with defaults: TGT, FP32, gamma 10, delta 1/n, seed 0x5C5C, auto tilde_tau. */

@@ -9,6 +9,7 @@
 // kGiant neighbours is cut into workgroup chunks whose partial sums a fix-up
 // pass adds in chunk order.
 #include "sc_internal.hpp"
+#include <hip/hip_ext.h>
 #include "tau.hpp"
 
 #include <cfloat>
@@ -127,9 +128,8 @@ struct RowArgs {
   const int32_t* slot_row;
   const double* inv_deg_d;
   AccJob acc;
-  // rows known to be zero in Yp (nz[u] == 0) are read from the zero row n
+  // rows known to be zero in Yp (nz[u] == 0, B = 64 only)
   const uint8_t* nz;
-  int n;
 };
 
 // gacc[k] += (Y[s][c] - Y[j][c]) / d_s for slot k = (s -> j), l <= tau_k (Eq. 9)
@@ -147,17 +147,36 @@ __device__ inline void accumulate_slot(const RowArgs<T>& a, const T* Y, int k) {
 // Sum over the 64-slot pieces first, first + step, ... of [beg, end) of the
 // neighbour rows of Yp (column c); lanes c, c+B, ... share a column and are
 // combined at the end.
-template <typename T, int B>
+template <typename T, int B, bool kSkip = false>
 __device__ inline T gather_pieces(const RowArgs<T>& a, const T* __restrict__ Yp, int beg, int end,
                                   int first, int step, int lane, int c, int gq) {
   constexpr int G = 64 / B;
   constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;   // gathers in flight per lane
+  static_assert(!kSkip || G == 1, "zero-row skipping needs one column per lane");
   T acc = T(0);
   for (int base = beg + 64 * first; base < end; base += 64 * step) {
     const int cnt = min(64, end - base);
-    int myu = lane < cnt ? a.col[base + lane] : 0;
-    if (a.nz && lane < cnt && !a.nz[myu]) myu = a.n;   // a zero row: read the zero row
-    if (G == 1) {
+    const int myu = lane < cnt ? a.col[base + lane] : 0;
+    if (kSkip) {
+      // gather only the slots whose row is nonzero, in slot order: the skipped
+      // rows are exact zeros, so the sum is that of the full slot loop
+      unsigned long long rem = __ballot(lane < cnt && a.nz[myu]);
+      while (rem) {
+        T v[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          v[q] = T(0);
+          if (rem) {
+            const int l = __builtin_ctzll(rem);
+            rem &= rem - 1ull;
+            const int u = __builtin_amdgcn_readlane(myu, l);
+            v[q] = Yp[static_cast<size_t>(u) * B + c];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) acc += v[q];
+      }
+    } else if (G == 1) {
       for (int jj = 0; jj < cnt; jj += kBatch) {
         T v[kBatch];
 #pragma unroll
@@ -231,8 +250,7 @@ __device__ inline void gather_run(const RowArgs<T>& a, const T* __restrict__ Yp,
   constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;
   const int nrows = tk.part;
   const int cnt = tk.end - tk.beg;
-  int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
-  if (a.nz && lane < cnt && !a.nz[myu]) myu = a.n;   // a zero row: read the zero row
+  const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
   const int myend = lane < nrows ? a.rowptr[tk.row + lane + 1] - tk.beg : 0;
   const T myinv = lane < nrows ? a.inv_deg[tk.row + lane] : T(0);
   T acc = T(0);
@@ -360,12 +378,63 @@ __global__ __launch_bounds__(kThreads) void k_twohop(RowArgs<T> a,
   if (gq == 0) Y[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
 }
 
+// gather_run when the rows flagged zero in nz are exact zeros: only the slots
+// of nonzero rows are gathered; each row's sum still closes in slot order and
+// rows whose slots are all skipped are written as zeros.
+template <typename T, int B>
+__device__ inline void gather_run_skip(const RowArgs<T>& a, const T* __restrict__ Yp,
+                                       const Task& tk, int lane, T* __restrict__ Yn) {
+  constexpr int kBatch = sizeof(T) == 4 ? 32 : 16;
+  const int nrows = tk.part;
+  const int cnt = tk.end - tk.beg;
+  const int myu = lane < cnt ? a.col[tk.beg + lane] : 0;
+  const int myend = lane < nrows ? a.rowptr[tk.row + lane + 1] - tk.beg : 0;
+  const T myinv = lane < nrows ? a.inv_deg[tk.row + lane] : T(0);
+  unsigned long long rem = __ballot(lane < cnt && a.nz[myu]);
+  T acc = T(0);
+  int ri = 0;
+  int bnd = __builtin_amdgcn_readlane(myend, 0);
+  while (rem) {
+    T v[kBatch];
+    int sl[kBatch];   // wave-uniform slot of each gather, 64 = none
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      v[q] = T(0);
+      sl[q] = 64;
+      if (rem) {
+        const int l = __builtin_ctzll(rem);
+        rem &= rem - 1ull;
+        const int u = __builtin_amdgcn_readlane(myu, l);
+        v[q] = Yp[static_cast<size_t>(u) * B + lane];
+        sl[q] = l;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      if (sl[q] < 64) {
+        while (bnd <= sl[q]) {   // close the rows that end before this slot
+          Yn[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+          acc = T(0);
+          ++ri;
+          bnd = __builtin_amdgcn_readlane(myend, ri & 63);
+        }
+        acc += v[q];
+      }
+    }
+  }
+  for (; ri < nrows; ++ri) {
+    Yn[static_cast<size_t>(tk.row + ri) * B + lane] = acc * bcast(myinv, ri);
+    acc = T(0);
+  }
+}
+
 // ------------------------------------------------------------------ dense propagation
 // Workgroups [0, nwg): heavy rows and giant-row chunks; then wave tasks; then
 // the accumulation of the step held in Yp (fused, saves a launch).  Register
 // use is held to 6 waves per SIMD: more waves with shallower gather batches run
 // the kernel faster alone but slow the concurrent tail of the block pipeline.
-template <typename T, int B>
+// kSkip (B = 64): rows with nz[u] == 0 are exact zeros in Yp and are not gathered.
+template <typename T, int B, bool kSkip>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_propagate(RowArgs<T> a, const T* __restrict__ Yp,
                                                         T* __restrict__ Yn) {
   if (static_cast<int>(blockIdx.x) >= a.row_blocks) {
@@ -379,7 +448,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))
   const int gq = lane / B;
   if (static_cast<int>(blockIdx.x) < a.nwg) {
     const Task tk = a.wg_tasks[blockIdx.x];
-    const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, wave, kWavesPerBlock, lane, c, gq);
+    const T sum =
+        gather_pieces<T, B, kSkip>(a, Yp, tk.beg, tk.end, wave, kWavesPerBlock, lane, c, gq);
     wg_finish<T, B>(a, tk, sum, wave, lane, Yn);
     return;
   }
@@ -388,10 +458,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))
     if (t >= a.nptasks) return;
     const Task tk = a.ptasks[t];
     if (tk.end - tk.beg <= 64) {
-      gather_run<T, B>(a, Yp, tk, lane, Yn);
+      if (kSkip)
+        gather_run_skip<T, B>(a, Yp, tk, lane, Yn);
+      else
+        gather_run<T, B>(a, Yp, tk, lane, Yn);
       return;
     }
-    const T sum = gather_pieces<T, B>(a, Yp, tk.beg, tk.end, 0, 1, lane, c, gq);
+    const T sum = gather_pieces<T, B, kSkip>(a, Yp, tk.beg, tk.end, 0, 1, lane, c, gq);
     Yn[static_cast<size_t>(tk.row) * B + c] = sum * a.inv_deg[tk.row];
     return;
   }
@@ -546,7 +619,6 @@ RowArgs<T> row_args(const DeviceGraph& g, int B, T* partials, const AccJob& acc)
   a.inv_deg_d = g.inv_deg_d;
   a.acc = acc;
   a.nz = nullptr;
-  a.n = g.n;
   return a;
 }
 
@@ -576,11 +648,19 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                                 const AccJob& acc, hipStream_t st, const uint8_t* nz) {
+                                 const AccJob& acc, hipStream_t st, const uint8_t* nz,
+                                 hipEvent_t ev_start, hipEvent_t ev_stop) {
   RowArgs<T> a = row_args<T>(g, B, partials, acc);
-  a.nz = B == 64 ? nz : nullptr;
   const int blocks = a.row_blocks + acc_blocks(acc);
-  SC_DISPATCH_B(B, (k_propagate<T, kB><<<blocks, kThreads, 0, st>>>(a, Yp, Yn)));
+  if (B == 64 && nz) {
+    a.nz = nz;
+    hipExtLaunchKernelGGL(k_propagate<T, 64, true>, dim3(blocks), dim3(kThreads), 0, st,
+                          ev_start, ev_stop, 0, a, Yp, Yn);
+  } else {
+    SC_DISPATCH_B(B, (hipExtLaunchKernelGGL(k_propagate<T, kB, false>, dim3(blocks),
+                                            dim3(kThreads), 0, st, ev_start, ev_stop, 0, a, Yp,
+                                            Yn)));
+  }
   return hipGetLastError();
 }
 
@@ -641,9 +721,11 @@ template hipError_t launch_twohop<float>(const DeviceGraph&, int, const unsigned
 template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigned long long*,
                                           const unsigned*, double*, double*, uint8_t*, hipStream_t);
 template hipError_t launch_propagate_rows<float>(const DeviceGraph&, int, const float*, float*,
-                                                float*, const AccJob&, hipStream_t, const uint8_t*);
+                                                float*, const AccJob&, hipStream_t, const uint8_t*,
+                                                hipEvent_t, hipEvent_t);
 template hipError_t launch_propagate_rows<double>(const DeviceGraph&, int, const double*, double*,
-                                                 double*, const AccJob&, hipStream_t, const uint8_t*);
+                                                 double*, const AccJob&, hipStream_t,
+                                                 const uint8_t*, hipEvent_t, hipEvent_t);
 template hipError_t launch_fixup<float>(const DeviceGraph&, int, const float*, float*, hipStream_t);
 template hipError_t launch_fixup<double>(const DeviceGraph&, int, const double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,

@@ -554,11 +554,7 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
       g->Y[i] = nullptr;
     }
     g->ybytes = 0;
-    // n rows of state plus the zero row n (never written; 64 columns of 8 bytes)
-    for (int i = 0; i < 4; ++i) {
-      HIP_TRY(hipMalloc(&g->Y[i], yb + 64 * sizeof(double)));
-      HIP_TRY(hipMemset(static_cast<char*>(g->Y[i]) + yb, 0, 64 * sizeof(double)));
-    }
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipMalloc(&g->Y[i], yb));
     g->ybytes = yb;
   }
   if (!g->nz) {

@@ -500,9 +500,9 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   hipEvent_t t0 = nullptr, t1 = nullptr, kb = nullptr, ke = nullptr;
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
-  if (timing && !replay) {
-    HIP_TRY(hipEventCreate(&kb));
-    HIP_TRY(hipEventCreate(&ke));
+  if (timing && !replay) {   // timing only: no system-scope fence around the kernels
+    HIP_TRY(hipEventCreateWithFlags(&kb, hipEventDisableSystemFence));
+    HIP_TRY(hipEventCreateWithFlags(&ke, hipEventDisableSystemFence));
   }
   struct EvGuard {
     hipEvent_t* e[4];

@@ -149,11 +149,13 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 
 // The two launches of launch_propagate, separately: the row gathers (giant
 // rows leave chunk sums in partials) and the giant-row fix-up.  With B = 64
-// and nz, neighbours u with nz[u] == 0 are read from Yp's zero row n (Yp holds
-// n + 1 rows): adding an exact zero leaves every sum unchanged.
+// and nz, neighbours u with nz[u] == 0 are not gathered (their rows of Yp are
+// exact zeros, so every sum is unchanged).  Non-null ev_start / ev_stop take
+// the start and end times of the row-gather kernel itself.
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
-                                 const AccJob& acc, hipStream_t st, const uint8_t* nz = nullptr);
+                                 const AccJob& acc, hipStream_t st, const uint8_t* nz = nullptr,
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename T>
 hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
 
