@@ -106,6 +106,8 @@ typedef struct sc_stats {
   int64_t prop_timed;      /* launches whose times prop_ms sums (SC_TIME_KERNELS times
                               every 15th counted launch with events that take the
                               kernel's own start and end)                          */
+  double host_ms;          /* host time spent issuing the block loop (the GPU work
+                              queued behind it runs meanwhile)                     */
 } sc_stats;
 
 /* Fill *o with defaults: TGT, FP32, gamma 10, delta 1/n, seed 0x5C5C, auto tilde_tau. */

@@ -570,21 +570,22 @@ __global__ __launch_bounds__(kThreads) void k_walks(
     // the two walks of the pair advance in lockstep so their loads overlap
     int pos0 = s, pos1 = j;
     double sum0 = 0.0, sum1 = 0.0;
-    U32x4 w0, w1;
-    for (int t = 0; t < len; ++t) {
-      if ((t & 3) == 0) {
-        const uint32_t hi = static_cast<uint32_t>(t >> 2);
-        w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
-                           static_cast<uint32_t>(r), hi, k0, k1);
-        w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
-                           static_cast<uint32_t>(r), (1u << 31) | hi, k0, k1);
+    for (int t4 = 0; t4 < len; t4 += 4) {   // four steps per Philox draw
+      const uint32_t hi = static_cast<uint32_t>(t4 >> 2);
+      const U32x4 w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                                     static_cast<uint32_t>(r), hi, k0, k1);
+      const U32x4 w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                                     static_cast<uint32_t>(r), (1u << 31) | hi, k0, k1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (t4 + u >= len) break;
+        const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
+        const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
+        pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[u], static_cast<uint32_t>(e0 - b0)))];
+        pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[u], static_cast<uint32_t>(e1 - b1)))];
+        sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + c]);
+        sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + c]);
       }
-      const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
-      const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
-      pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[t & 3], static_cast<uint32_t>(e0 - b0)))];
-      pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[t & 3], static_cast<uint32_t>(e1 - b1)))];
-      sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + c]);
-      sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + c]);
     }
     acc += (sum0 - sum1) * inv_deg[s];   // X of Eq. 11
   }
@@ -697,21 +698,25 @@ __global__ __launch_bounds__(kThreads) void k_walks_flat(
       const int j = col[k];
       int pos0 = s, pos1 = j;
       double sum0 = 0.0, sum1 = 0.0;
-      U32x4 w0, w1;
-      for (int t = 0; t < len; ++t) {
-        if ((t & 3) == 0) {
-          const uint32_t h = static_cast<uint32_t>(t >> 2);
-          w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
-                             static_cast<uint32_t>(r), h, k0, k1);
-          w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
-                             static_cast<uint32_t>(r), (1u << 31) | h, k0, k1);
+      // four steps per Philox draw, the word of each step a compile-time index
+      // (a run-time index would put the draw in scratch memory)
+      for (int t4 = 0; t4 < len; t4 += 4) {
+        const uint32_t h = static_cast<uint32_t>(t4 >> 2);
+        const U32x4 w0 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                                       static_cast<uint32_t>(r), h, k0, k1);
+        const U32x4 w1 = philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(j),
+                                       static_cast<uint32_t>(r), (1u << 31) | h, k0, k1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t4 + u >= len) break;
+          // the two walks of the pair advance in lockstep so their loads overlap
+          const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
+          const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
+          pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[u], static_cast<uint32_t>(e0 - b0)))];
+          pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[u], static_cast<uint32_t>(e1 - b1)))];
+          sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + cc]);
+          sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + cc]);
         }
-        const int b0 = rowptr[pos0], e0 = rowptr[pos0 + 1];
-        const int b1 = rowptr[pos1], e1 = rowptr[pos1 + 1];
-        pos0 = col[b0 + static_cast<int>(pick_neighbour(w0.w[t & 3], static_cast<uint32_t>(e0 - b0)))];
-        pos1 = col[b1 + static_cast<int>(pick_neighbour(w1.w[t & 3], static_cast<uint32_t>(e1 - b1)))];
-        sum0 += static_cast<double>(Y[static_cast<size_t>(pos0) * B + cc]);
-        sum1 += static_cast<double>(Y[static_cast<size_t>(pos1) * B + cc]);
       }
       x = (sum0 - sum1) * inv_deg[s];   // X of Eq. 11
     }

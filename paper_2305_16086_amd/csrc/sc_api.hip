@@ -6,6 +6,7 @@
 // buffers, chooses launch parameters and sequences the launches.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -774,6 +775,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   hipStream_t sb = g->tail_stream;
   HIP_TRY(hipEventRecord(g->pipe_ev[0], st));
   HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[0], 0));
+  const auto host0 = std::chrono::steady_clock::now();
   for (int b = 0; b < nblocks; ++b) {
     int s0, kbeg, kend, tmax;
     block_range(b, &s0, &kbeg, &kend, &tmax);
@@ -803,6 +805,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     HIP_TRY(hipEventRecord(g->pipe_ev[3 + pair], sb));
     R.st = st;
   }
+  R.stats.host_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
   HIP_TRY(hipEventRecord(g->pipe_ev[0], sb));
   HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[0], 0));
   R.po = 0;

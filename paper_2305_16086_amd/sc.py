@@ -83,6 +83,7 @@ class ScStats(C.Structure):
         ("total_ms", C.c_double),
         ("fallback_edges", C.c_int64),
         ("prop_timed", C.c_int64),
+        ("host_ms", C.c_double),
     ]
 
     def as_dict(self):
