@@ -546,19 +546,16 @@ __global__ __launch_bounds__(256) void k_work_totals(int kbeg, int kend, int til
   }
 }
 
-// One wave per slot; lanes take walk pairs r = lane, lane + 64, ...
+// The walks of slot k = (s -> j) by one wave, lanes taking walk pairs r = lane,
+// lane + 64, ...; gacc[k] += their mean (Eq. 11).
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_walks(
-    int kbeg, int kend, int s0, int tilde, unsigned k0, unsigned k1,
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ slot_row, const int32_t* __restrict__ deg,
-    const double* __restrict__ inv_deg, const T* __restrict__ Y, const int32_t* __restrict__ tau,
-    const long long* __restrict__ nr, const long long* __restrict__ ctl,
-    double* __restrict__ gacc) {
-  if (ctl != nullptr && ctl[1] != 0) return;   // the flattened kernels took this block
-  const int lane = threadIdx.x & 63;
-  const int k = kbeg + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (k >= kend) return;
+__device__ inline void slot_walks(int k, int lane, int s0, int tilde, unsigned k0, unsigned k1,
+                                  const int32_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col,
+                                  const int32_t* __restrict__ slot_row,
+                                  const double* __restrict__ inv_deg, const T* __restrict__ Y,
+                                  const int32_t* __restrict__ tau,
+                                  const long long* __restrict__ nr, double* __restrict__ gacc) {
   const long long n_r = nr[k];
   if (n_r <= 0) return;
   const int len = tau[k] - tilde;
@@ -593,13 +590,27 @@ __global__ __launch_bounds__(kThreads) void k_walks(
   if (lane == 0) gacc[k] += acc / static_cast<double>(n_r);
 }
 
+// One wave per slot (the walk tail without chunk scratch).
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_walks(
+    int kbeg, int kend, int s0, int tilde, unsigned k0, unsigned k1,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ slot_row, const double* __restrict__ inv_deg,
+    const T* __restrict__ Y, const int32_t* __restrict__ tau, const long long* __restrict__ nr,
+    double* __restrict__ gacc) {
+  const int lane = threadIdx.x & 63;
+  const int k = kbeg + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (k >= kend) return;
+  slot_walks<T, B>(k, lane, s0, tilde, k0, k1, rowptr, col, slot_row, inv_deg, Y, tau, nr, gacc);
+}
+
 // ---------------------------------------------------------------- flattened walks
 // The walk pairs of a block's half-edges are cut into chunks of 64 pairs
 // (chunk_off: exclusive prefix of ceil(n_r / 64) over the block's slots, one
 // workgroup); waves take contiguous ranges of chunks, one pair per lane, and
 // store each chunk's sum (fixed butterfly); a last pass adds a slot's chunk
 // sums in chunk order.  ctl[0] = number of chunks, ctl[1] = 1 when they fit
-// the partial-sum buffer (else the per-slot kernel runs instead).
+// the partial-sum buffer (else the same grid walks one slot per wave).
 constexpr int kScanThreads = 256;   // one small workgroup: schedules beside the traversal kernels
 constexpr int kScanPer = 8;
 
@@ -662,12 +673,18 @@ __global__ __launch_bounds__(kThreads) void k_walks_flat(
     const int32_t* __restrict__ slot_row, const double* __restrict__ inv_deg,
     const T* __restrict__ Y, const int32_t* __restrict__ tau, const long long* __restrict__ nr,
     const long long* __restrict__ chunk_off, const long long* __restrict__ ctl,
-    double* __restrict__ part) {
-  if (ctl[1] == 0) return;
-  const long long total = ctl[0];
+    double* __restrict__ part, double* __restrict__ gacc) {
   const int lane = threadIdx.x & 63;
   const long long nwaves = static_cast<long long>(gridDim.x) * kWavesPerBlock;
   const long long w = static_cast<long long>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+  if (ctl[1] == 0) {
+    // the chunks do not fit the partial-sum buffer: one wave per slot instead
+    for (long long k = kbeg + w; k < kend; k += nwaves)
+      slot_walks<T, B>(static_cast<int>(k), lane, s0, tilde, k0, k1, rowptr, col, slot_row,
+                       inv_deg, Y, tau, nr, gacc);
+    return;
+  }
+  const long long total = ctl[0];
   const long long per = (total + nwaves - 1) / nwaves;
   const long long c0 = w * per;
   const long long c1 = min(total, c0 + per);
@@ -826,24 +843,22 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
   long long* off = reinterpret_cast<long long*>(ws.chunk_off);
   long long* ctl = reinterpret_cast<long long*>(ws.ctl);
   const bool flat = ws.chunk_off && ws.part && ws.ctl;
-  if (flat) {
-    k_walk_scan<<<1, kScanThreads, 0, st>>>(kbeg, kend, nr, off, ws.capacity, ctl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    SC_DISPATCH_B(B, (k_walks_flat<T, kB><<<kWalkBlocks, kThreads, 0, st>>>(
+  if (!flat) {   // no chunk scratch: one wave per slot
+    SC_DISPATCH_B(B, (k_walks<T, kB><<<grid_for(kend - kbeg, kWavesPerBlock), kThreads, 0, st>>>(
                           kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row,
-                          g.inv_deg_d, Y, tau_slot, nr, off, ctl, ws.part)));
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_walk_finish<<<grid_for(kend - kbeg, 256), 256, 0, st>>>(kbeg, kend, nr, off, ctl, ws.part,
-                                                             gacc);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+                          g.inv_deg_d, Y, tau_slot, nr, gacc)));
+    return hipGetLastError();
   }
-  // per-slot kernel: the whole job without scratch, or blocks whose chunks do not fit
-  SC_DISPATCH_B(B, (k_walks<T, kB><<<grid_for(kend - kbeg, kWavesPerBlock), kThreads, 0, st>>>(
-                        kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row, g.deg,
-                        g.inv_deg_d, Y, tau_slot, nr, flat ? ctl : nullptr, gacc)));
+  k_walk_scan<<<1, kScanThreads, 0, st>>>(kbeg, kend, nr, off, ws.capacity, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SC_DISPATCH_B(B, (k_walks_flat<T, kB><<<kWalkBlocks, kThreads, 0, st>>>(
+                        kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row, g.inv_deg_d,
+                        Y, tau_slot, nr, off, ctl, ws.part, gacc)));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_walk_finish<<<grid_for(kend - kbeg, 256), 256, 0, st>>>(kbeg, kend, nr, off, ctl, ws.part,
+                                                           gacc);
   return hipGetLastError();
 }
 
