@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=48)
-    p.add_argument("--form", choices=["plain", "batch", "learned"], default="plain",
+    p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps"], default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
                         "persistent launch against one graph at a time; learned: the "
                         "learned tail closure against plain TGT+ on BA-100k")
@@ -59,6 +59,9 @@ def parse():
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="plain: one untimed device-to-device copy of this many MB (a kernel "
                         "of known traffic, to scale HBM counters)")
+    p.add_argument("--er-eps", type=float, default=0.05, help="er: error bound eps")
+    p.add_argument("--check-edges", type=int, default=16,
+                   help="er/eps: sampled edges checked against exact SC (conjugate gradients)")
     p.add_argument("--replay", action="store_true", help="batch: replay a captured hipGraph")
     p.add_argument("--tune-json", default=None, help="batch: tuning table (written if absent)")
     return p.parse_args()
@@ -358,6 +361,163 @@ def learned_form(a):
     print(json.dumps(line), flush=True)
 
 
+def exact_sc_sampled(n, u, v, ids):
+    """Exact SC of the edges ids: (e_i - e_j)^T L^+ (e_i - e_j) by Jacobi-preconditioned
+    conjugate gradients on the Laplacian in float64 (the right-hand sides sum to
+    zero, so the singular system is consistent)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    uu = np.concatenate([u, v])
+    vv = np.concatenate([v, u])
+    A = sp.csr_matrix((np.ones(len(uu)), (uu, vv)), shape=(n, n))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    Lap = sp.diags(d) - A
+    M = sp.diags(1.0 / d)
+    out = np.empty(len(ids))
+    for t, e in enumerate(ids):
+        b = np.zeros(n)
+        b[u[e]] = 1.0
+        b[v[e]] = -1.0
+        x, info = sla.cg(Lap, b, rtol=1e-12, atol=0.0, maxiter=10 * n, M=M)
+        if info != 0:
+            raise RuntimeError(f"conjugate gradients did not converge on edge {e}")
+        out[t] = x[u[e]] - x[v[e]]
+    return out
+
+
+def timed_calls(sc, g, eps, o, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        sc.sc_all_edges_ex(g, eps, 0, o, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = sc.sc_all_edges_ex(g, eps, 0, o, out=out)[1]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, st
+
+
+def er_form(a):
+    """Scalability on Erdos-Renyi graphs G(n, m) (seed 1): n = 10^4 with m = 0.2, 0.5,
+    1, 2, 5 x 10^6, and m = 10^6 with n = 2, 5, 10, 20, 50 x 10^3 (the sizes of the
+    paper's scalability tables); TGT+, FP32 propagation, block 64, eps = --er-eps.
+    Graph build and lambda* are preprocessing (not timed).  Accuracy on
+    --check-edges sampled edges against exact SC by conjugate gradients."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    rng = np.random.default_rng(7)
+    rows = []
+    for series, sizes in (("edges", gg.ER_EDGES_SERIES), ("nodes", gg.ER_NODES_SERIES)):
+        for n, m_target in sizes:
+            n, u, v = gg.erdos_renyi_nm(n, m_target, SEED)
+            m = len(u)
+            g = sc.sc_build_graph(n, u, v)
+            out = torch.empty(m, dtype=torch.float64, device=dev)
+            o = sc.sc_default_options(method=sc.SC_TGT_PLUS, precision=0, block=BLOCK,
+                                      stream=stream.cuda_stream)
+            dt, st = timed_calls(sc, g, a.er_eps, o, out, a.steps, a.warmup)
+            ids = rng.choice(m, size=min(a.check_edges, m), replace=False)
+            err = float(np.abs(out.cpu().numpy()[ids] - exact_sc_sampled(n, u, v, ids)).max())
+            g.free()
+            row = {"series": series, "n": n, "m": m, "ms": 1e3 * dt, "edges_per_s": m / dt,
+                   "max_abs_err_sampled": err, "L_used": st["L_used"],
+                   "tilde_tau": st["tilde_tau"], "lambda_star": st["lambda_star"],
+                   "walks": st["walks"]}
+            rows.append(row)
+            print(f"[er] {series} n={n} m={m}: {1e3 * dt:.1f} ms, err {err:.2e}, "
+                  f"L={st['L_used']} tilde={st['tilde_tau']}", file=sys.stderr, flush=True)
+    head = rows[[r["series"] == "nodes" and r["n"] == 10_000 for r in rows].index(True)]
+    line = {
+        "metric": "all-edge SC edges/sec (TGT+) on Erdos-Renyi graphs",
+        "value": head["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Erdos-Renyi G(n, m) scalability series, seed {SEED}; "
+                               f"value = the n=10^4, m=10^6 graph; TGT+, eps={a.er_eps}, "
+                               f"FP32 propagation, block 64", "eps": a.er_eps, "rows": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def eps_form(a):
+    """Error-bound sweep eps in {0.05, 0.02, 0.01, 0.005}: TGT+ and TGT on ba_100k
+    (max and mean error on the 2048 edges whose exact SC the oracle stored), and
+    TGT+ on Barabasi-Albert stand-ins with the node and edge counts of the paper's
+    datasets (attachment m/n rounded; --check-edges sampled edges against exact SC
+    by conjugate gradients)."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    eps_list = (0.05, 0.02, 0.01, 0.005)
+    rows = []
+    graph = gg.workload("ba_100k", SEED)
+    n, u, v = graph
+    m = len(u)
+    gz = np.load(GOLDEN)
+    g = sc.sc_build_graph(n, u, v)
+    out = torch.empty(m, dtype=torch.float64, device=dev)
+    for method, mname in ((sc.SC_TGT_PLUS, "tgt_plus"), (sc.SC_TGT, "tgt")):
+        for eps in eps_list:
+            o = sc.sc_default_options(method=method, precision=0, block=BLOCK,
+                                      stream=stream.cuda_stream)
+            dt, st = timed_calls(sc, g, eps, o, out, a.steps, a.warmup)
+            e = np.abs(out.cpu().numpy()[gz["edge_ids"]] - gz["sc"])
+            rows.append({"graph": "ba_100k", "n": n, "m": m, "method": mname, "eps": eps,
+                         "ms": 1e3 * dt, "edges_per_s": m / dt, "max_abs_err": float(e.max()),
+                         "mean_abs_err": float(e.mean()), "checked_edges": len(e),
+                         "L_used": st["L_used"], "tilde_tau": st["tilde_tau"]})
+            print(f"[eps] ba_100k {mname} eps={eps}: {1e3 * dt:.1f} ms, max err {e.max():.2e}",
+                  file=sys.stderr, flush=True)
+    g.free()
+    rng = np.random.default_rng(11)
+    for name, n_ds, m_ds in (("facebook-shaped", 4_039, 88_234), ("hepph-shaped", 34_401, 420_784),
+                             ("slashdot-shaped", 77_360, 469_180),
+                             ("twitch-shaped", 168_114, 6_797_557)):
+        k = max(1, round(m_ds / n_ds))
+        n, u, v = gg.barabasi_albert(n_ds, k, SEED)
+        m = len(u)
+        g = sc.sc_build_graph(n, u, v)
+        out = torch.empty(m, dtype=torch.float64, device=dev)
+        ids = rng.choice(m, size=min(a.check_edges, m), replace=False)
+        ref = exact_sc_sampled(n, u, v, ids)
+        for eps in eps_list:
+            o = sc.sc_default_options(method=sc.SC_TGT_PLUS, precision=0, block=BLOCK,
+                                      stream=stream.cuda_stream)
+            dt, st = timed_calls(sc, g, eps, o, out, a.steps, a.warmup)
+            e = np.abs(out.cpu().numpy()[ids] - ref)
+            rows.append({"graph": name, "n": n, "m": m, "attach": k, "method": "tgt_plus",
+                         "eps": eps, "ms": 1e3 * dt, "edges_per_s": m / dt,
+                         "max_abs_err": float(e.max()), "mean_abs_err": float(e.mean()),
+                         "checked_edges": len(e), "L_used": st["L_used"],
+                         "tilde_tau": st["tilde_tau"]})
+            print(f"[eps] {name} n={n} m={m} eps={eps}: {1e3 * dt:.1f} ms, "
+                  f"max err {e.max():.2e}", file=sys.stderr, flush=True)
+        g.free()
+    head = [r for r in rows if r["graph"] == "ba_100k" and r["method"] == "tgt_plus"
+            and r["eps"] == 0.01][0]
+    line = {
+        "metric": "all-edge SC edges/sec across error bounds (TGT+, TGT)",
+        "value": head["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "eps sweep on ba_100k (value: TGT+ at eps=0.01) and on "
+                               "Barabasi-Albert stand-ins of the paper's dataset sizes",
+                   "rows": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -368,6 +528,12 @@ def main():
         return
     if a.form == "learned":
         learned_form(a)
+        return
+    if a.form == "er":
+        er_form(a)
+        return
+    if a.form == "eps":
+        eps_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc

@@ -15,6 +15,9 @@ from .graphs import (  # noqa: F401
     tree_plus_gnp,
     gnp_connected,
     barabasi_albert,
+    erdos_renyi_nm,
+    ER_EDGES_SERIES,
+    ER_NODES_SERIES,
     king_grid,
     mixed_batch,
     rmat_lcc,

@@ -132,6 +132,12 @@ def _gnp_pairs(n, p, rng):
     """G(n,p) edge set: Binomial(C(n,2), p) distinct uniform pairs."""
     total = n * (n - 1) // 2
     k = int(rng.binomial(total, p))
+    return _distinct_pairs(n, k, rng)
+
+
+def _distinct_pairs(n, k, rng):
+    """k distinct node pairs (a < b) drawn uniformly from the C(n,2) pairs."""
+    total = n * (n - 1) // 2
     if k == 0:
         return np.zeros(0, np.int64), np.zeros(0, np.int64)
     got = np.zeros(0, dtype=np.int64)
@@ -191,6 +197,36 @@ def gnp_connected(n: int, avg_deg: float, seed: int):
             extra_v.append(giant[rng.integers(0, len(giant))])
         u, v = canonical_edges(n, np.concatenate([u, extra_u]), np.concatenate([v, extra_v]))
     return n, u, v
+
+
+def erdos_renyi_nm(n: int, m: int, seed: int):
+    """Uniform G(n, m): m distinct pairs drawn uniformly.  Each component other
+    than the giant one is joined to it by one random edge (so m grows by the
+    number of such components, none at the densities used here)."""
+    if m > n * (n - 1) // 2:
+        raise ValueError("m exceeds the number of node pairs")
+    rng = np.random.default_rng(seed)
+    u, v = _distinct_pairs(n, m, rng)
+    u, v = canonical_edges(n, u, v)
+    ncomp, lab = csg.connected_components(_adj(n, u, v), directed=False)
+    if ncomp > 1:
+        big = np.argmax(np.bincount(lab))
+        giant = np.flatnonzero(lab == big)
+        extra_u, extra_v = [], []
+        for c in range(ncomp):
+            if c == big:
+                continue
+            members = np.flatnonzero(lab == c)
+            extra_u.append(members[rng.integers(0, len(members))])
+            extra_v.append(giant[rng.integers(0, len(giant))])
+        u, v = canonical_edges(n, np.concatenate([u, extra_u]), np.concatenate([v, extra_v]))
+    return n, u, v
+
+
+# Scalability series of Erdos-Renyi graphs: n fixed at 10^4 with m varied, and
+# m fixed at 10^6 with n varied (the sizes of the paper's scalability tables).
+ER_EDGES_SERIES = [(10_000, m) for m in (200_000, 500_000, 1_000_000, 2_000_000, 5_000_000)]
+ER_NODES_SERIES = [(n, 1_000_000) for n in (2_000, 5_000, 10_000, 20_000, 50_000)]
 
 
 def barabasi_albert(n: int, m_attach: int, seed: int):

@@ -256,6 +256,28 @@ def test_ba_100k_tgt_plus_sampled(sc):
     np.testing.assert_allclose(out[sub], ref[sub], atol=FP32_TOL, rtol=0)
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_dense_erdos_renyi_rows(sc, precision):
+    """G(n, m) with n = 700, m = 105,000 (degrees 250-340: most rows are
+    workgroup tasks): TGT against the oracle's truncated traversal on every
+    edge, and TGT+ against the oracle's replay of the same walks on the edges
+    of 12 sources."""
+    graph = gg.erdos_renyi_nm(700, 105_000, 2)
+    n, u, v = graph
+    m = len(u)
+    G = otgt.Graph(n, u, v)
+    tol = FP64_TOL if precision else FP32_TOL
+    out, st, tau, _, _ = run(sc, graph, 1e-3, 0, method=sc.SC_TGT, precision=precision)
+    np.testing.assert_allclose(out, otgt.truncated_sc(G, tau), atol=tol, rtol=0)
+    out, st, tau, tt, nr = run(sc, graph, 0.3, 7, method=sc.SC_TGT_PLUS, precision=precision,
+                               tilde_tau=2, seed=99)
+    srcs = np.arange(0, n, 59)[:12]
+    _, _, ref = otgt.tgt_plus_replay(G, tau, tt, nr[:m], nr[m:], seed=99, sources=srcs)
+    both = np.isin(u, srcs) & np.isin(v, srcs)   # both halves replayed
+    assert both.sum() > 0
+    np.testing.assert_allclose(out[both], ref[both], atol=tol, rtol=0)
+
+
 @pytest.mark.parametrize("precision,block", [(1, 64), (0, 64), (0, 16)])
 def test_giant_and_heavy_rows(sc, precision, block):
     """A hub with 5,500 neighbours (cut into workgroup chunks and a fix-up
