@@ -56,6 +56,9 @@ enum {
 #define SC_TIME_KERNELS 0x4u /* time a sample of propagation launches with HIP events */
 #define SC_GRAPH_REPLAY 0x8u /* sc_batch_all_edges: record the device work as a hipGraph
                                 on the first call, replay it on later identical calls */
+#define SC_TAU_SPECTRAL 0x10u /* automatic truncation (L = 0) by CalTau, Algorithm 1, with
+                                 the graph's spectrum (sc_compute_spectrum / sc_set_spectrum)
+                                 instead of the lambda*-bound; SC_TGT and SC_TGT_PLUS */
 
 /* methods (sc_options.method) */
 #define SC_TGT 0       /* Algorithm 2: traversal to tau for every source */
@@ -141,6 +144,35 @@ void sc_free_graph(sc_graph* g);
  * extreme Ritz value plus its residual norm.
  */
 int sc_lambda_star(sc_graph* g, double* lam);
+
+/* ---- spectrum for CalTau (Algorithm 1, Theorem 3.2, Eq. 6-8) ----------------
+ * The omega eigenpairs (lambda_k, phi_k) of N = D^-1/2 A D^-1/2 of largest
+ * |lambda|: lambda[0] = 1 with phi_0 = sqrt(d / 2m), then |lambda| descending.
+ * phi is node-major: phi[x * omega + k].  CalTau uses pairs 2 .. omega-1
+ * (1-based) exactly and bounds the others by |lambda_omega|; the bound holds if
+ * no eigenvalue left out is larger in magnitude than |lambda_omega|.
+ * The graph keeps one spectrum (replaced by every set/compute call). */
+
+/* Lanczos with full re-orthogonalisation on the device (the trivial pair
+ * deflated), checked every 25 steps, stopping when the omega - 1 Ritz pairs of
+ * largest |theta| have residual estimates <= tol (<= 0: 1e-8) or after max_iter
+ * steps (<= 0: 2048; also capped by n - 1 and a 16 GiB basis).  Keeps the
+ * longest prefix of pairs within tol: *omega_kept (<= omega) and their largest
+ * residual estimate *max_residual (either may be NULL).  A single-vector Krylov
+ * space finds one vector per repeated eigenvalue, so graphs with repeated
+ * eigenvalues among the top ones need sc_set_spectrum instead.
+ * omega in [2, 256] (clamped to n).  SC_EINVAL if no pair converges. */
+int sc_compute_spectrum(sc_graph* g, int omega, int max_iter, double tol, int* omega_kept,
+                        double* max_residual);
+
+/* Load a spectrum computed elsewhere: lambda[omega], phi[n * omega] (host, node-major,
+ * copied).  SC_EINVAL unless 2 <= omega <= min(n, 256), lambda[0] = 1, the others in
+ * (-1, 1) and ordered by |lambda| descending. */
+int sc_set_spectrum(sc_graph* g, int omega, const double* lambda, const double* phi);
+
+/* *omega = stored pair count (0: none); lambda[omega] and phi[n * omega] (host) are
+ * filled when not NULL. */
+int sc_get_spectrum(const sc_graph* g, int* omega, double* lambda, double* phi);
 
 /*
  * All-edge SC with default options (FP32 propagation, TGT when L > 0 or

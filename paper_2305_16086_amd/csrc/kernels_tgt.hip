@@ -56,6 +56,111 @@ __global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* 
   tau_row[x] = tmax;
 }
 
+// ------------------------------------------------------------------ CalTau (Algorithm 1)
+// One wave per row x; for every slot (x -> j) the lanes hold the eigenpairs
+// k = 2 .. omega-1 (1-based; up to kMaxOmega / 64 per lane) and the sums of
+// Eq. 7 and Eq. 8 close with a fixed butterfly, so both halves of an edge get
+// the same tau.  lam[omega], phi[n][omega] node-major, pair 1 the trivial one.
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_caltau(
+    int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ deg, const double* __restrict__ lam,
+    const double* __restrict__ phi, int omega, double eps_tau, int max_L,
+    int32_t* __restrict__ tau_slot, int32_t* __restrict__ tau_row) {
+  constexpr int P = kMaxOmega / 64;
+  const int x = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (x >= n) return;
+  bool on[P];
+  double lk[P], ax[P];
+  const double dx = static_cast<double>(deg[x]);
+  const double sx = sqrt(dx);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int k = lane + 64 * p;   // 0-based index; the captured pairs are 1 .. omega-2
+    on[p] = k >= 1 && k <= omega - 2;
+    lk[p] = on[p] ? lam[k] : 0.0;
+    ax[p] = on[p] ? phi[static_cast<size_t>(x) * omega + k] / sx : 0.0;
+  }
+  const double lw = fabs(lam[omega - 1]);
+  const double shrink = 1.0 - lw * lw;
+  const double log_inv = log(1.0 / lw);
+  int tmax = 0;
+  for (int s = rowptr[x]; s < rowptr[x + 1]; ++s) {
+    const int j = col[s];
+    const double dj = static_cast<double>(deg[j]);
+    const double sj = sqrt(dj);
+    double coef[P], pw[P], sq[P];
+    double ups = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int k = lane + 64 * p;
+      const double a = on[p] ? ax[p] - phi[static_cast<size_t>(j) * omega + k] / sj : 0.0;
+      const double w = a * a;
+      ups += w * (1.0 + lk[p]);
+      coef[p] = on[p] ? w / (1.0 - lk[p]) : 0.0;
+      sq[p] = lk[p] * lk[p];
+      pw[p] = sq[p];   // lambda_k^(t+1) at t = 1
+    }
+    ups = wave_sum_d(ups);                                 // Eq. 7
+    const double num = 1.0 / dx + 1.0 / dj - 2.0 / (dx * dj) - ups;
+    int t = 1;
+    while (t <= max_L) {
+      double dl = 0.0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) dl += coef[p] * pw[p];
+      const double delta = wave_sum_d(dl);                 // Eq. 8 at t
+      bool more;                                           // t <= Eq. 6 (Algorithm 1 line 5)
+      if (eps_tau - delta <= 0.0) {
+        more = true;                                       // Eq. 6 = +infinity
+      } else if (num <= 0.0) {
+        more = false;                                      // Eq. 6 = -infinity
+      } else {
+        const double f = ceil(log(num / ((eps_tau - delta) * shrink)) / log_inv - 1.0);
+        more = static_cast<double>(t) <= f;
+      }
+      if (!more) break;
+      t += 2;
+#pragma unroll
+      for (int p = 0; p < P; ++p) pw[p] *= sq[p];
+    }
+    const int tau = t > max_L ? max_L : t;
+    if (lane == 0) tau_slot[s] = tau;
+    tmax = tau > tmax ? tau : tmax;
+  }
+  if (lane == 0) tau_row[x] = tmax;
+}
+
+// Ritz vectors of the Lanczos basis: phi[x][1 + c] = sum_i V[i + 1][x] Y[i][c]
+// for c < p (Y: steps x p32 row-major, zero-padded to a multiple of 32
+// columns); column 0 of phi is V's column 0 (the trivial eigenvector).
+
+__global__ __launch_bounds__(256) void k_ritz(int64_t n, int64_t ld, const double* __restrict__ V,
+                                              int steps, const double* __restrict__ Y, int p32,
+                                              int p, int omega, double* __restrict__ phi) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (x >= n) return;
+  const int c0 = blockIdx.y * kRitzCols;
+  double acc[kRitzCols];
+#pragma unroll
+  for (int c = 0; c < kRitzCols; ++c) acc[c] = 0.0;
+  for (int i = 0; i < steps; ++i) {
+    const double v = V[static_cast<size_t>(i + 1) * ld + x];
+    const double* yr = Y + static_cast<size_t>(i) * p32 + c0;
+#pragma unroll
+    for (int c = 0; c < kRitzCols; ++c) acc[c] += v * yr[c];
+  }
+#pragma unroll
+  for (int c = 0; c < kRitzCols; ++c)
+    if (c0 + c < p) phi[static_cast<size_t>(x) * omega + 1 + c0 + c] = acc[c];
+  if (blockIdx.y == 0) phi[static_cast<size_t>(x) * omega] = V[x];
+}
+
 // ------------------------------------------------------------------ indicator masks
 // Waves [0, B) mark bit c of mask[u] (and the node's bit in anymask) for every
 // u in N(s_set + c) in buffer `buf`; waves [B, 2B) clear what block s_clear
@@ -574,6 +679,23 @@ hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, i
                       int32_t* tau_slot, int32_t* tau_row, hipStream_t st) {
   k_tau<<<grid_for(g.n, 256), 256, 0, st>>>(g.n, g.rowptr, g.col, g.deg, L, eps_tau, lam, max_L,
                                              tau_slot, tau_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_caltau(const DeviceGraph& g, const double* lam, const double* phi, int omega,
+                         double eps_tau, int max_L, int32_t* tau_slot, int32_t* tau_row,
+                         hipStream_t st) {
+  if (omega < 2 || omega > kMaxOmega) return hipErrorInvalidValue;
+  k_caltau<<<grid_for(g.n, kWavesPerBlock), kThreads, 0, st>>>(
+      g.n, g.rowptr, g.col, g.deg, lam, phi, omega, eps_tau, max_L, tau_slot, tau_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz(int64_t n, int64_t ld, const double* V, int steps, const double* Y,
+                       int p32, int p, int omega, double* phi, hipStream_t st) {
+  if (p32 % kRitzCols != 0 || p > p32 || 1 + p > omega) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(p32 / kRitzCols));
+  k_ritz<<<grid, 256, 0, st>>>(n, ld, V, steps, Y, p32, p, omega, phi);
   return hipGetLastError();
 }
 

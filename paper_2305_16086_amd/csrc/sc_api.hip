@@ -6,6 +6,7 @@
 // buffers, chooses launch parameters and sequences the launches.
 
 #include <algorithm>
+#include <limits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -66,6 +67,8 @@ void sc_graph::release() {
   dev_free(tau_slot);
   dev_free(tau_row);
   dev_free(nr_slot);
+  dev_free(spec_lam);
+  dev_free(spec_phi);
   dev_free(cs);
   if (colscratch) (void)hipFree(colscratch);
   colscratch = nullptr;
@@ -385,6 +388,118 @@ __global__ void k_scale_into(const double* __restrict__ w, double s, double* __r
   if (x < n) dst[x] = w[x] * s;
 }
 
+// Lanczos start for N = D^-1/2 A D^-1/2: column 0 of V holds the top
+// eigenvector sqrt(d / 2m) (eigenvalue 1, deflated by the re-orthogonalisation),
+// column 1 a fixed pseudo-random unit vector orthogonal to it; sid = 1/sqrt(d).
+hipError_t lanczos_start(const sc::DeviceGraph& dg, const int32_t* deg_host, double* V, int64_t ld,
+                         double* sid, hipStream_t st) {
+  const int64_t n = dg.n;
+  std::vector<double> hv(n), sidh(n);
+  const double two_m = static_cast<double>(dg.nslots);
+  for (int64_t x = 0; x < n; ++x) {
+    hv[x] = std::sqrt(deg_host[x] / two_m);
+    sidh[x] = 1.0 / std::sqrt(static_cast<double>(deg_host[x]));
+  }
+  std::vector<double> v0(n);
+  uint64_t z = 0x9E3779B97F4A7C15ull;
+  double dot = 0.0;
+  for (int64_t x = 0; x < n; ++x) {
+    z += 0x9E3779B97F4A7C15ull;
+    uint64_t r = z;
+    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+    r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+    r ^= r >> 31;
+    v0[x] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    dot += v0[x] * hv[x];
+  }
+  double nrm = 0.0;
+  for (int64_t x = 0; x < n; ++x) {
+    v0[x] -= dot * hv[x];
+    nrm += v0[x] * v0[x];
+  }
+  nrm = std::sqrt(nrm);
+  for (int64_t x = 0; x < n; ++x) v0[x] /= nrm;
+  hipError_t e = hipMemcpy(V, hv.data(), n * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(V + ld, v0.data(), n * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(sid, sidh.data(), n * sizeof(double), hipMemcpyHostToDevice);
+  (void)st;
+  return e;
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix (diagonal d[0..k), off-diagonal
+// e[0..k-1)) by implicit QL iterations with Wilkinson-type shifts (Wilkinson and
+// Reinsch; Golub and Van Loan, implicit symmetric tridiagonal QR).  d receives
+// the eigenvalues (unordered).  z (k x k row-major), if given, receives the
+// eigenvectors as columns; zlast, if given, their last components only.
+// Returns false if an eigenvalue needs more than 60 iterations.
+bool tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<double>* z,
+                   std::vector<double>* zlast) {
+  const int k = static_cast<int>(d.size());
+  e.resize(k, 0.0);
+  e[k - 1] = 0.0;
+  if (z) {
+    z->assign(static_cast<size_t>(k) * k, 0.0);
+    for (int i = 0; i < k; ++i) (*z)[static_cast<size_t>(i) * k + i] = 1.0;
+  }
+  if (zlast) {
+    zlast->assign(k, 0.0);
+    (*zlast)[k - 1] = 1.0;
+  }
+  const double ulp = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < k; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m < k - 1; ++m)   // first negligible off-diagonal at or after l
+        if (std::fabs(e[m]) <= ulp * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+      if (m == l) break;
+      if (iter == 60) return false;
+      // shift from the leading 2 x 2 block, then chase the bulge from m up to l
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      bool split = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = sn * e[i];
+        const double b = cs * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {   // the matrix splits: deflate and restart from l
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          split = true;
+          break;
+        }
+        sn = f / r;
+        cs = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * sn + 2.0 * cs * b;
+        p = sn * r;
+        d[i + 1] = g + p;
+        g = cs * r - b;
+        if (z) {
+          for (int q = 0; q < k; ++q) {
+            double* row = z->data() + static_cast<size_t>(q) * k;
+            const double t = row[i + 1];
+            row[i + 1] = sn * row[i] + cs * t;
+            row[i] = cs * row[i] - sn * t;
+          }
+        }
+        if (zlast) {
+          const double t = (*zlast)[i + 1];
+          (*zlast)[i + 1] = sn * (*zlast)[i] + cs * t;
+          (*zlast)[i] = cs * (*zlast)[i] - sn * t;
+        }
+      }
+      if (split) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  return true;
+}
+
 // extreme Ritz estimate: max over the two ends of |theta| + residual
 double ritz_bound(const std::vector<double>& alpha, const std::vector<double>& beta, int k,
                   double beta_last, double* worst_res) {
@@ -437,36 +552,7 @@ int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipS
     cleanup();
     return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP, "lanczos allocation failed");
   }
-  // column 0: the top eigenvector sqrt(d)/sqrt(2m) (eigenvalue 1), deflated throughout
-  std::vector<double> hv(n), sidh(n);
-  const double two_m = static_cast<double>(dg.nslots);
-  for (int64_t x = 0; x < n; ++x) {
-    hv[x] = std::sqrt(deg_host[x] / two_m);
-    sidh[x] = 1.0 / std::sqrt(static_cast<double>(deg_host[x]));
-  }
-  // start vector: fixed pseudo-random, made orthogonal to column 0
-  std::vector<double> v0(n);
-  uint64_t z = 0x9E3779B97F4A7C15ull;
-  double dot = 0.0;
-  for (int64_t x = 0; x < n; ++x) {
-    z += 0x9E3779B97F4A7C15ull;
-    uint64_t r = z;
-    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
-    r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
-    r ^= r >> 31;
-    v0[x] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
-    dot += v0[x] * hv[x];
-  }
-  double nrm = 0.0;
-  for (int64_t x = 0; x < n; ++x) {
-    v0[x] -= dot * hv[x];
-    nrm += v0[x] * v0[x];
-  }
-  nrm = std::sqrt(nrm);
-  for (int64_t x = 0; x < n; ++x) v0[x] /= nrm;
-  HIP_TRY(hipMemcpy(V, hv.data(), n * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(V + ld, v0.data(), n * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(sid, sidh.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(lanczos_start(dg, deg_host, V, ld, sid, st));
 
   std::vector<double> alpha, beta, hh(kmax + 2);
   double result = -1.0;
@@ -515,6 +601,218 @@ int sc::graph_lambda_star(sc_graph* g, hipStream_t st, double* lam) {
     g->lambda_star = v;
   }
   *lam = g->lambda_star;
+  return SC_OK;
+}
+
+// Lanczos with full re-orthogonalisation (twice) on N = D^-1/2 A D^-1/2 with
+// the trivial eigenvector deflated.  Every 25 steps the Ritz values of the
+// tridiagonal matrix are checked: the run stops when the omega - 1 of largest
+// |theta| have residual estimates |beta_j y_j| <= tol (or after max_iter steps,
+// or when the Krylov space is exhausted).  The longest prefix (|theta|
+// descending) of pairs within tol is kept, with the trivial pair in front.
+int sc::lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipStream_t st,
+                         int* kept, double* worst) {
+  const sc::DeviceGraph& dg = g->d;
+  const int64_t n = dg.n;
+  const int64_t ld = n;
+  // the basis is held whole: at most ~16 GiB of it
+  const int64_t cap = std::max<int64_t>(omega + 8, (int64_t(16) << 30) / (8 * n) - 2);
+  const int kmax = static_cast<int>(std::min<int64_t>({n - 1, static_cast<int64_t>(max_iter), cap}));
+  double *V = nullptr, *w = nullptr, *h = nullptr, *sid = nullptr, *Yd = nullptr;
+  auto cleanup = [&]() {
+    dev_free(V);
+    dev_free(w);
+    dev_free(h);
+    dev_free(sid);
+    dev_free(Yd);
+  };
+  hipError_t e = dev_alloc(&V, static_cast<size_t>(kmax + 2) * ld);
+  if (e == hipSuccess) e = dev_alloc(&w, n);
+  if (e == hipSuccess) e = dev_alloc(&h, kmax + 2);
+  if (e == hipSuccess) e = dev_alloc(&sid, n);
+  if (e == hipSuccess) e = lanczos_start(dg, g->deg_h.data(), V, ld, sid, st);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP, "spectrum: allocation failed");
+  }
+  const int want = omega - 1;
+  // Ritz pairs ordered by |theta| descending (ties: theta descending)
+  auto order_of = [](const std::vector<double>& th) {
+    std::vector<int> idx(th.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = static_cast<int>(i);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+      const double fa = std::fabs(th[a]), fb = std::fabs(th[b]);
+      return fa > fb || (fa == fb && th[a] > th[b]);
+    });
+    return idx;
+  };
+  std::vector<double> alpha, beta, hh(kmax + 2);
+  const unsigned grid = static_cast<unsigned>((n + 255) / 256);
+  int steps = 0;
+  double b_last = 0.0;
+  for (int j = 1; j <= kmax; ++j) {
+    const double* vj = V + static_cast<size_t>(j) * ld;
+    HIP_TRY(sc::launch_nmat_spmv(dg, sid, vj, w, st));
+    double a_j = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      HIP_TRY(sc::launch_multi_dot(V, j + 1, ld, w, n, h, st));
+      HIP_TRY(hipMemcpyAsync(hh.data(), h, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      a_j += hh[j];
+      HIP_TRY(sc::launch_multi_axpy(V, j + 1, ld, h, w, n, st));
+    }
+    HIP_TRY(sc::launch_multi_dot(w, 1, ld, w, n, h, st));
+    HIP_TRY(hipMemcpyAsync(hh.data(), h, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double b_j = std::sqrt(std::max(hh[0], 0.0));
+    alpha.push_back(a_j);
+    steps = j;
+    b_last = b_j;
+    const bool exhausted = b_j < 1e-12 || j == kmax;
+    if (exhausted) break;
+    if (j % 25 == 0 && j >= want) {
+      std::vector<double> th = alpha, zl;
+      if (!tridiag_eigen(th, beta, nullptr, &zl)) break;
+      const std::vector<int> idx = order_of(th);
+      bool done = true;
+      for (int c = 0; c < want && done; ++c) done = std::fabs(b_j * zl[idx[c]]) <= tol;
+      if (done) break;
+    }
+    beta.push_back(b_j);
+    k_scale_into<<<grid, 256, 0, st>>>(w, 1.0 / b_j, V + static_cast<size_t>(j + 1) * ld, n);
+    HIP_TRY(hipGetLastError());
+  }
+  // Ritz pairs of the final tridiagonal matrix
+  std::vector<double> th = alpha, Z;
+  beta.resize(steps - 1);
+  if (!tridiag_eigen(th, beta, &Z, nullptr)) {
+    cleanup();
+    return fail(SC_EINVAL, "spectrum: tridiagonal eigenvalues did not converge");
+  }
+  const std::vector<int> idx = order_of(th);
+  const bool exact = b_last < 1e-12;   // invariant subspace: the Ritz pairs are eigenpairs
+  int p = 0;
+  double wres = 0.0;
+  while (p < want && p < steps) {
+    const double r = exact ? 0.0 : std::fabs(b_last * Z[static_cast<size_t>(steps - 1) * steps + idx[p]]);
+    if (r > tol) break;
+    wres = std::max(wres, r);
+    ++p;
+  }
+  if (p == 0) {
+    cleanup();
+    return fail(SC_EINVAL, "spectrum: no Ritz pair reached the tolerance (raise max_iter)");
+  }
+  const int om = p + 1;
+  const int p32 = (p + kRitzCols - 1) / kRitzCols * kRitzCols;
+  std::vector<double> Y(static_cast<size_t>(steps) * p32, 0.0);
+  for (int i = 0; i < steps; ++i)
+    for (int c = 0; c < p; ++c) Y[static_cast<size_t>(i) * p32 + c] = Z[static_cast<size_t>(i) * steps + idx[c]];
+  std::vector<double> lam(om);
+  lam[0] = 1.0;
+  for (int c = 0; c < p; ++c) lam[1 + c] = th[idx[c]];
+  double* lam_d = nullptr;
+  double* phi_d = nullptr;
+  e = dev_alloc(&Yd, Y.size());
+  if (e == hipSuccess) e = dev_alloc(&lam_d, om);
+  if (e == hipSuccess) e = dev_alloc(&phi_d, static_cast<size_t>(n) * om);
+  if (e == hipSuccess) e = hipMemcpy(Yd, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(lam_d, lam.data(), om * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sc::launch_ritz(n, ld, V, steps, Yd, p32, p, om, phi_d, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) {
+    dev_free(lam_d);
+    dev_free(phi_d);
+    return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
+                std::string("spectrum: ") + hipGetErrorString(e));
+  }
+  dev_free(g->spec_lam);
+  dev_free(g->spec_phi);
+  g->spec_lam = lam_d;
+  g->spec_phi = phi_d;
+  g->spec_omega = om;
+  g->spec_lam_h = lam;
+  ++g->spec_version;
+  *kept = om;
+  *worst = wres;
+  return SC_OK;
+}
+
+extern "C" int sc_compute_spectrum(sc_graph* g, int omega, int max_iter, double tol,
+                                   int* omega_kept, double* max_residual) {
+  if (!g) return fail(SC_EINVAL, "graph is NULL");
+  if (omega < 2 || omega > sc::kMaxOmega) return fail(SC_EINVAL, "omega must lie in [2, 256]");
+  if (omega > g->d.n) omega = static_cast<int>(g->d.n);
+  if (max_iter <= 0) max_iter = 2048;
+  if (!(tol > 0.0)) tol = 1e-8;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != g->device) (void)hipSetDevice(g->device);
+  int kept = 0;
+  double worst = 0.0;
+  const int rc = sc::lanczos_spectrum(g, omega, max_iter, tol, nullptr, &kept, &worst);
+  if (cur != g->device) (void)hipSetDevice(cur);
+  if (rc) return rc;
+  if (omega_kept) *omega_kept = kept;
+  if (max_residual) *max_residual = worst;
+  return SC_OK;
+}
+
+extern "C" int sc_set_spectrum(sc_graph* g, int omega, const double* lambda, const double* phi) {
+  if (!g || !lambda || !phi) return fail(SC_EINVAL, "NULL argument");
+  if (omega < 2 || omega > sc::kMaxOmega || omega > g->d.n)
+    return fail(SC_EINVAL, "omega must lie in [2, min(n, 256)]");
+  if (std::fabs(lambda[0] - 1.0) > 1e-8)
+    return fail(SC_EINVAL, "lambda[0] must be the trivial eigenvalue 1");
+  for (int k = 1; k < omega; ++k) {
+    if (!(std::fabs(lambda[k]) < 1.0))
+      return fail(SC_EINVAL, "non-trivial eigenvalues must lie in (-1, 1)");
+    if (k >= 2 && std::fabs(lambda[k]) > std::fabs(lambda[k - 1]) * (1.0 + 1e-12))
+      return fail(SC_EINVAL, "eigenvalues must be ordered by |lambda| descending");
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != g->device) (void)hipSetDevice(g->device);
+  const size_t cells = static_cast<size_t>(g->d.n) * omega;
+  double* lam_d = nullptr;
+  double* phi_d = nullptr;
+  hipError_t e = sc::dev_alloc(&lam_d, omega);
+  if (e == hipSuccess) e = sc::dev_alloc(&phi_d, cells);
+  if (e == hipSuccess) e = hipMemcpy(lam_d, lambda, omega * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(phi_d, phi, cells * sizeof(double), hipMemcpyHostToDevice);
+  if (cur != g->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    sc::dev_free(lam_d);
+    sc::dev_free(phi_d);
+    return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
+                std::string("set spectrum: ") + hipGetErrorString(e));
+  }
+  sc::dev_free(g->spec_lam);
+  sc::dev_free(g->spec_phi);
+  g->spec_lam = lam_d;
+  g->spec_phi = phi_d;
+  g->spec_omega = omega;
+  g->spec_lam_h.assign(lambda, lambda + omega);
+  ++g->spec_version;
+  return SC_OK;
+}
+
+extern "C" int sc_get_spectrum(const sc_graph* g, int* omega, double* lambda, double* phi) {
+  if (!g || !omega) return fail(SC_EINVAL, "NULL argument");
+  *omega = g->spec_omega;
+  if (g->spec_omega == 0) return SC_OK;
+  if (lambda) std::memcpy(lambda, g->spec_lam_h.data(), g->spec_omega * sizeof(double));
+  if (phi) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    const hipError_t e = hipMemcpy(phi, g->spec_phi,
+                                   static_cast<size_t>(g->d.n) * g->spec_omega * sizeof(double),
+                                   hipMemcpyDeviceToHost);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(SC_EHIP, std::string("get spectrum: ") + hipGetErrorString(e));
+  }
   return SC_OK;
 }
 
@@ -650,11 +948,17 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   HIP_TRY(hipEventCreate(&t1));
   HIP_TRY(hipEventRecord(t0, st));
 
-  // truncation policy
+  // truncation policy: uniform L, CalTau with the graph's spectrum (Algorithm 1),
+  // or the lambda*-bound (Algorithm 1 line 1)
   double lam = 0.0;
   int Lodd = 0;
+  const bool spectral = L == 0 && (o.flags & SC_TAU_SPECTRAL) != 0;
+  if (spectral && g->spec_omega < 2)
+    return fail(SC_EINVAL, "SC_TAU_SPECTRAL needs a spectrum (sc_compute_spectrum or sc_set_spectrum)");
   if (L > 0) {
     Lodd = (L % 2 == 1) ? L : L + 1;
+  } else if (spectral) {
+    lam = std::fabs(g->spec_lam_h[1]);
   } else {
     if (o.lambda_star > 0.0) {
       lam = o.lambda_star;
@@ -666,7 +970,11 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   }
   R.stats.lambda_star = lam;
   const double eps_tau = plus ? eps / 2.0 : eps;
-  HIP_TRY(sc::launch_tau(g->d, Lodd, eps_tau, lam, max_L, g->tau_slot, g->tau_row, st));
+  if (spectral)
+    HIP_TRY(sc::launch_caltau(g->d, g->spec_lam, g->spec_phi, g->spec_omega, eps_tau, max_L,
+                              g->tau_slot, g->tau_row, st));
+  else
+    HIP_TRY(sc::launch_tau(g->d, Lodd, eps_tau, lam, max_L, g->tau_slot, g->tau_row, st));
   std::vector<int32_t> tau_row(n);
   HIP_TRY(hipMemcpyAsync(tau_row.data(), g->tau_row, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -702,7 +1010,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     // Eq. 13 constant; m counts distinct edges
     coef = 8.0 * std::log(static_cast<double>(g->d.nslots) / delta) / (eps * eps);
     HIP_TRY(hipMemsetAsync(g->nr_slot, 0, g->rowptr_h[n] * sizeof(int64_t), st));
-    const sc_graph::PlanKey key{eps, L, max_L, lam, B, static_cast<int>(sizeof(T)), gamma, delta};
+    const sc_graph::PlanKey key{eps,  L,     max_L, lam, B, static_cast<int>(sizeof(T)), gamma,
+                                delta, spectral ? g->spec_version : 0};
     if (o.tilde_tau >= 0) {
       tilde = std::min(o.tilde_tau, Lmax);
     } else if (g->plan_valid && g->plan_key == key) {
@@ -892,6 +1201,8 @@ extern "C" int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options*
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != g->device) (void)hipSetDevice(g->device);
+  if (opt.method == SC_LEARNED && (opt.flags & SC_TAU_SPECTRAL))
+    return fail(SC_ENOTIMPL, "SC_TAU_SPECTRAL is not supported with SC_LEARNED");
   int rc;
   if (opt.method == SC_LEARNED)
     rc = sc::run_learned(g, eps, opt, out, st);

@@ -594,6 +594,8 @@ int run_dispatch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
                  double* const* out, sc_stats* st, float* kernel_ms) {
   if (!(eps > 0.0 && eps < 1.0)) return fail(SC_EINVAL, "eps must lie in (0, 1)");
   if (o.method != SC_TGT) return fail(SC_ENOTIMPL, "batches run TGT (method 0) only");
+  if (o.flags & SC_TAU_SPECTRAL)
+    return fail(SC_ENOTIMPL, "batches use the lambda*-bound (SC_TAU_SPECTRAL not supported)");
   if (o.precision != 0 && o.precision != 1) return fail(SC_EINVAL, "precision must be 0 or 1");
   if (o.block != 0 && !valid_block(o.block))
     return fail(SC_EINVAL, "batch block must be 0 or 1, 2, 4, 8, 16, 32, 64");
@@ -736,6 +738,8 @@ extern "C" int sc_batch_autotune(sc_batch* b, double eps, const int32_t* L, cons
                                  const char* json_path) {
   if (!b || !o) return fail(SC_EINVAL, "NULL argument");
   if (o->method != SC_TGT) return fail(SC_ENOTIMPL, "batches run TGT (method 0) only");
+  if (o->flags & SC_TAU_SPECTRAL)
+    return fail(SC_ENOTIMPL, "batches use the lambda*-bound (SC_TAU_SPECTRAL not supported)");
   const size_t tsize = o->precision == 1 ? sizeof(double) : sizeof(float);
   // buckets present, each with its graphs (largest first)
   struct Bucket {

@@ -42,6 +42,13 @@ struct sc_graph {
   std::vector<int32_t> rowptr_h;
   std::vector<int32_t> deg_h;
   double lambda_star = -1.0;
+  // spectrum for CalTau (Algorithm 1): spec_omega eigenpairs of D^-1/2 A D^-1/2,
+  // |lambda| descending after the trivial pair; phi node-major [n][spec_omega]
+  int spec_omega = 0;
+  int spec_version = 0;                 // bumped on every change (keys the cached plan)
+  double* spec_lam = nullptr;           // device [spec_omega]
+  double* spec_phi = nullptr;           // device [n * spec_omega]
+  std::vector<double> spec_lam_h;
 
   // work buffers, grown on demand
   void* Y[4] = {nullptr, nullptr, nullptr, nullptr};   // two pairs (block pipeline)
@@ -72,9 +79,11 @@ struct sc_graph {
     double lam;
     int B, tsize, gamma;
     double delta;
+    int tau_policy;   // 0: lambda*-bound, else the spectrum version used by CalTau
     bool operator==(const PlanKey& o) const {
       return eps == o.eps && L == o.L && max_L == o.max_L && lam == o.lam && B == o.B &&
-             tsize == o.tsize && gamma == o.gamma && delta == o.delta;
+             tsize == o.tsize && gamma == o.gamma && delta == o.delta &&
+             tau_policy == o.tau_policy;
     }
   };
   PlanKey plan_key{};
@@ -117,6 +126,9 @@ int upload_csr(const HostCSR& h, DeviceGraph& d);
 // New handle owning an upload of h (h.rowptr and h.deg are moved into it).
 int graph_from_csr(HostCSR& h, sc_graph** out);
 int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out);
+// Lanczos for the omega eigenpairs of largest |lambda| (stores the converged prefix in g)
+int lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipStream_t st, int* kept,
+                     double* worst);
 
 int ensure_buffers(sc_graph* g, int B, size_t tsize);
 int ensure_pipeline(sc_graph* g);

@@ -131,6 +131,18 @@ hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int i
 
 // tau per slot: uniform L (odd) when L > 0, else the lambda* bound of
 // Theorem 3.2 with Upsilon = Delta = 0.  Also the per-row maximum.
+// CalTau (Algorithm 1, Eq. 6-8) for every slot with the omega eigenpairs of
+// D^-1/2 A D^-1/2 of largest |lambda| (lam[omega], phi[n][omega] node-major on
+// the device, pair 0 the trivial one); tau capped at the odd max_L.
+constexpr int kMaxOmega = 256;
+hipError_t launch_caltau(const DeviceGraph& g, const double* lam, const double* phi, int omega,
+                         double eps_tau, int max_L, int32_t* tau_slot, int32_t* tau_row,
+                         hipStream_t st);
+// Ritz vectors phi[x][1..p] = V[:, 1..steps] Y (Y: steps x p32 row-major, p32 a multiple of
+// kRitzCols), phi[x][0] = V[x]
+constexpr int kRitzCols = 32;
+hipError_t launch_ritz(int64_t n, int64_t ld, const double* V, int steps, const double* Y,
+                       int p32, int p, int omega, double* phi, hipStream_t st);
 hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
                       int32_t* tau_slot, int32_t* tau_row, hipStream_t st);
 

@@ -29,6 +29,7 @@ SC_MERGE_DUPS = 0x2
 SC_DEVICE_PTRS = 0x1
 SC_TIME_KERNELS = 0x4
 SC_GRAPH_REPLAY = 0x8
+SC_TAU_SPECTRAL = 0x10
 
 SC_TGT = 0
 SC_TGT_PLUS = 1
@@ -111,6 +112,13 @@ def _load():
     lib.sc_free_graph.restype = None
     lib.sc_lambda_star.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
     lib.sc_lambda_star.restype = C.c_int
+    lib.sc_compute_spectrum.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    lib.sc_compute_spectrum.restype = C.c_int
+    lib.sc_set_spectrum.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    lib.sc_set_spectrum.restype = C.c_int
+    lib.sc_get_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
+    lib.sc_get_spectrum.restype = C.c_int
     lib.sc_all_edges.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_void_p]
     lib.sc_all_edges.restype = C.c_int
     lib.sc_all_edges_ex.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(ScOptions),
@@ -178,7 +186,8 @@ EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_gr
             "sc_mlp_free", "sc_mlp_get", "sc_mlp_set", "sc_closure_dataset",
             "sc_closure_features", "sc_mlp_train", "sc_mlp_grad", "sc_mlp_predict",
             "sc_build_batch", "sc_batch_size", "sc_batch_graph", "sc_free_batch",
-            "sc_batch_all_edges", "sc_batch_blocks", "sc_batch_autotune", "sc_batch_load_tuning"]
+            "sc_batch_all_edges", "sc_batch_blocks", "sc_batch_autotune", "sc_batch_load_tuning",
+            "sc_compute_spectrum", "sc_set_spectrum", "sc_get_spectrum"]
 
 
 def _check(rc, where):
@@ -260,6 +269,40 @@ def sc_lambda_star(g: Graph) -> float:
     lam = C.c_double()
     _check(_lib.sc_lambda_star(g.handle, C.byref(lam)), "sc_lambda_star")
     return lam.value
+
+
+def sc_compute_spectrum(g: Graph, omega: int = 128, max_iter: int = 0, tol: float = 0.0):
+    """GPU Lanczos for the omega eigenpairs of D^-1/2 A D^-1/2 of largest |lambda|
+    (kept in the graph for SC_TAU_SPECTRAL).  Returns (pairs kept, largest residual)."""
+    kept = C.c_int()
+    res = C.c_double()
+    _check(_lib.sc_compute_spectrum(g.handle, int(omega), int(max_iter), float(tol),
+                                    C.byref(kept), C.byref(res)), "sc_compute_spectrum")
+    return kept.value, res.value
+
+
+def sc_set_spectrum(g: Graph, lam, phi):
+    """Load eigenpairs computed elsewhere: lam[omega], phi[n, omega] (node-major)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    omega = len(lam)
+    if phi.shape != (g.n, omega):
+        raise ValueError(f"phi must have shape ({g.n}, {omega})")
+    _check(_lib.sc_set_spectrum(g.handle, omega, lam.ctypes.data, phi.ctypes.data),
+           "sc_set_spectrum")
+
+
+def sc_get_spectrum(g: Graph):
+    """The graph's spectrum: (lam[omega], phi[n, omega]), or None if there is none."""
+    omega = C.c_int()
+    _check(_lib.sc_get_spectrum(g.handle, C.byref(omega), None, None), "sc_get_spectrum")
+    if omega.value == 0:
+        return None
+    lam = np.empty(omega.value, np.float64)
+    phi = np.empty((g.n, omega.value), np.float64)
+    _check(_lib.sc_get_spectrum(g.handle, C.byref(omega), lam.ctypes.data, phi.ctypes.data),
+           "sc_get_spectrum")
+    return lam, phi
 
 
 def sc_all_edges(g: Graph, eps: float, L: int, out=None) -> np.ndarray:

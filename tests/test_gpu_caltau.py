@@ -1,0 +1,166 @@
+"""GPU parity of CalTau (Algorithm 1) and of the device spectrum.
+
+* the CalTau kernel against the oracle on the same eigenpairs (the oracle's
+  dense eigensolver, loaded with sc_set_spectrum): every tau equal, except
+  where an evaluated Eq. 6 value lies within 1e-9 of an integer (the two sides
+  sum Eq. 7/8 in different orders), and then off by 2 at most; the traversal
+  with those tau against the oracle's (FP64 to 1e-12), within eps of the exact SC;
+* TGT+ with CalTau tau against the oracle's replay of the same walks;
+* the device Lanczos spectrum against the dense one (eigenvalues, residuals),
+  and end to end on a king grid: within eps of the exact SC with far shorter
+  truncation than the lambda*-bound;
+* error paths.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import caltau as ct
+from oracle import exact as ex
+from oracle import tgt as otgt
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_16086_amd import sc as scmod
+    return scmod
+
+
+def run(sc, g, eps, **opt):
+    tau = np.empty(g.m, np.int32)
+    tt = np.empty(g.n, np.int32)
+    nr = np.empty(2 * g.m, np.int64)
+    o = sc.sc_default_options(**opt)
+    out, st = sc.sc_all_edges_ex(g, eps, 0, o, tau_out=tau, tilde_tau_out=tt, nr_out=nr)
+    return out, st, tau, tt, nr
+
+
+GRAPHS = {
+    "tree_gnp": gg.tree_plus_gnp(300, 6.0, 5),
+    "ba": gg.barabasi_albert(400, 4, 6),
+    "king": gg.king_grid(400),   # repeated eigenvalues: fine when the pairs are given
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("omega", [2, 16, 64])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_caltau_kernel_matches_oracle(sc, name, omega, eps):
+    n, u, v = GRAPHS[name]
+    print(f"[gpu] caltau {name} omega={omega} eps={eps}", flush=True)
+    lam, phi = ct.top_spectrum(n, u, v, omega)
+    margins = []
+    want = ct.caltau(n, u, v, eps, lam, phi, max_L=255, margins=margins)
+    g = sc.sc_build_graph(n, u, v)
+    sc.sc_set_spectrum(g, lam, phi)
+    out, st, tau, _, _ = run(sc, g, eps, method=sc.SC_TGT, precision=1, flags=sc.SC_TAU_SPECTRAL)
+    g.free()
+    diff = tau != want
+    margins = np.array(margins)
+    assert np.all(margins[diff] < 1e-9), (np.flatnonzero(diff)[:5], tau[diff][:5], want[diff][:5])
+    assert np.all(np.abs(tau.astype(np.int64) - want) <= 2)
+    assert st["lambda_star"] == pytest.approx(abs(lam[1]), abs=0)
+    G = otgt.Graph(n, u, v)
+    np.testing.assert_allclose(out, otgt.truncated_sc(G, tau), atol=FP64_TOL, rtol=0)
+    if tau.max() < 255:   # the guarantee needs the uncapped tau (grids at omega = 2 hit the cap)
+        assert np.abs(out - ex.sc_pinv(n, u, v)).max() <= eps
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_caltau_tgt_plus_replay(sc, precision):
+    n, u, v = GRAPHS["ba"]
+    lam, phi = ct.top_spectrum(n, u, v, 32)
+    g = sc.sc_build_graph(n, u, v)
+    sc.sc_set_spectrum(g, lam, phi)
+    eps = 0.05
+    out, st, tau, tt, nr = run(sc, g, eps, method=sc.SC_TGT_PLUS, precision=precision,
+                               tilde_tau=2, seed=4242, flags=sc.SC_TAU_SPECTRAL)
+    g.free()
+    want = ct.caltau(n, u, v, eps / 2, lam, phi)   # TGT+ truncates at eps/2 (Algorithm 4)
+    assert np.mean(tau == want) >= 0.99
+    m = len(u)
+    _, _, ref = otgt.tgt_plus_replay(otgt.Graph(n, u, v), tau, tt, nr[:m], nr[m:], seed=4242)
+    np.testing.assert_allclose(out, ref, atol=FP64_TOL if precision else FP32_TOL, rtol=0)
+    assert np.abs(out - ex.sc_pinv(n, u, v)).max() <= eps
+
+
+@pytest.mark.parametrize("name,omega", [("tree_gnp", 24), ("ba", 24)])
+def test_device_spectrum_matches_dense(sc, name, omega):
+    n, u, v = GRAPHS[name]
+    print(f"[gpu] spectrum {name} omega={omega}", flush=True)
+    g = sc.sc_build_graph(n, u, v)
+    kept, res = sc.sc_compute_spectrum(g, omega, 0, 1e-10)
+    lam, phi = sc.sc_get_spectrum(g)
+    g.free()
+    assert kept == omega and len(lam) == omega and res <= 1e-10
+    ref, _ = ct.top_spectrum(n, u, v, omega)
+    np.testing.assert_allclose(lam, ref, atol=1e-9, rtol=0)
+    # residuals and orthonormality of the Ritz vectors, on the host
+    a = ex.adjacency_dense(n, u, v)
+    d = a.sum(1)
+    N = a / np.sqrt(np.outer(d, d))
+    r = N @ phi - phi * lam[None, :]
+    assert np.abs(r).max() <= 1e-7
+    np.testing.assert_allclose(phi.T @ phi, np.eye(omega), atol=1e-8, rtol=0)
+
+
+def test_device_spectrum_king_grid_end_to_end(sc):
+    n, u, v = gg.king_grid(1000)   # top eigenvalues simple (gaps >= 7e-4)
+    print("[gpu] king grid 1000, device spectrum", flush=True)
+    g = sc.sc_build_graph(n, u, v)
+    kept, res = sc.sc_compute_spectrum(g, 64, 0, 1e-10)
+    assert kept == 64
+    lam, _ = sc.sc_get_spectrum(g)
+    ref, _ = ct.top_spectrum(n, u, v, 64)
+    np.testing.assert_allclose(lam, ref, atol=1e-8, rtol=0)
+    exact = ex.sc_pinv(n, u, v)
+    eps = 1e-2
+    spec, st, tau, _, _ = run(sc, g, eps, method=sc.SC_TGT, precision=0, flags=sc.SC_TAU_SPECTRAL)
+    base, st0, tau0, _, _ = run(sc, g, eps, method=sc.SC_TGT, precision=0)
+    plus, _, _, _, _ = run(sc, g, eps, method=sc.SC_TGT_PLUS, precision=0,
+                           flags=sc.SC_TAU_SPECTRAL)
+    g.free()
+    assert np.abs(spec - exact).max() <= eps
+    assert np.abs(plus - exact).max() <= eps
+    assert np.abs(base - exact).max() <= eps
+    assert tau.mean() * 5 < tau0.mean()
+    print(f"mean tau {tau.mean():.1f} vs lambda*-bound {tau0.mean():.1f}", flush=True)
+
+
+def test_spectrum_errors_and_round_trip(sc):
+    n, u, v = GRAPHS["tree_gnp"]
+    g = sc.sc_build_graph(n, u, v)
+    assert sc.sc_get_spectrum(g) is None
+    with pytest.raises(sc.ScError) as e:
+        run(sc, g, 1e-2, method=sc.SC_TGT, flags=sc.SC_TAU_SPECTRAL)
+    assert e.value.code == sc.SC_EINVAL
+    lam, phi = ct.top_spectrum(n, u, v, 8)
+    unsorted = lam.copy()
+    unsorted[1], unsorted[2] = lam[2] * 0.5, lam[1]   # |lambda_3| > |lambda_2|
+    for bad_lam in (lam * 0.5, unsorted):
+        with pytest.raises(sc.ScError) as e:
+            sc.sc_set_spectrum(g, bad_lam, phi)
+        assert e.value.code == sc.SC_EINVAL
+    with pytest.raises(sc.ScError) as e:
+        sc.sc_set_spectrum(g, lam[:1], phi[:, :1])
+    assert e.value.code == sc.SC_EINVAL
+    sc.sc_set_spectrum(g, lam, phi)
+    lam2, phi2 = sc.sc_get_spectrum(g)
+    np.testing.assert_array_equal(lam2, lam)
+    np.testing.assert_array_equal(phi2, phi)
+    with pytest.raises(sc.ScError) as e:
+        sc.sc_compute_spectrum(g, 1)
+    assert e.value.code == sc.SC_EINVAL
+    g.free()
+    b = sc.sc_build_batch([GRAPHS["tree_gnp"]])
+    with pytest.raises(sc.ScError) as e:
+        sc.sc_batch_all_edges(b, 1e-2, None, sc.sc_default_options(flags=sc.SC_TAU_SPECTRAL))
+    assert e.value.code == sc.SC_ENOTIMPL
+    b.free()
