@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=48)
-    p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps"], default="plain",
+    p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau"],
+                   default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
                         "persistent launch against one graph at a time; learned: the "
                         "learned tail closure against plain TGT+ on BA-100k")
@@ -518,6 +519,68 @@ def eps_form(a):
     print(json.dumps(line), flush=True)
 
 
+def caltau_form(a):
+    """CalTau (Algorithm 1, omega = 128) against the lambda*-bound: the device
+    spectrum (preprocessing, timed apart), mean and largest tau, time per call and
+    error on sampled edges (exact SC by conjugate gradients).  Graphs: king grids
+    of 2,500 and 10,000 nodes (slow mixing; TGT at eps = 1e-2, the lambda*-bound
+    capped at max_L = 255 and so not certified) and ba_100k (TGT+ at eps = 1e-3)."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    rng = np.random.default_rng(5)
+    rows = []
+    for name, graph, method, eps in (("king_grid_2500", gg.king_grid(2500), sc.SC_TGT, 1e-2),
+                                     ("king_grid_10000", gg.king_grid(10_000), sc.SC_TGT, 1e-2),
+                                     ("ba_100k", gg.workload("ba_100k", SEED), sc.SC_TGT_PLUS, 1e-3)):
+        n, u, v = graph
+        m = len(u)
+        g = sc.sc_build_graph(n, u, v)
+        t0 = time.perf_counter()
+        kept, res = sc.sc_compute_spectrum(g, 128, 2048, 1e-8)
+        spec_s = time.perf_counter() - t0
+        lam, _ = sc.sc_get_spectrum(g)
+        out = torch.empty(m, dtype=torch.float64, device=dev)
+        tau = torch.empty(m, dtype=torch.int32, device=dev)
+        ids = rng.choice(m, size=min(a.check_edges, m), replace=False)
+        ref = exact_sc_sampled(n, u, v, ids)
+        for policy, flags in (("lambda_star", 0), ("caltau", sc.SC_TAU_SPECTRAL)):
+            o = sc.sc_default_options(method=method, precision=0, block=BLOCK, flags=flags,
+                                      stream=stream.cuda_stream)
+            dt, st = timed_calls(sc, g, eps, o, out, a.steps, a.warmup)
+            sc.sc_all_edges_ex(g, eps, 0, o, out=out, tau_out=tau)
+            torch.cuda.synchronize()
+            t = tau.cpu().numpy()
+            err = float(np.abs(out.cpu().numpy()[ids] - ref).max())
+            rows.append({"graph": name, "n": n, "m": m, "policy": policy,
+                         "method": "tgt_plus" if method == sc.SC_TGT_PLUS else "tgt", "eps": eps,
+                         "ms": 1e3 * dt, "edges_per_s": m / dt, "tau_mean": float(t.mean()),
+                         "tau_max": int(t.max()), "capped": bool(t.max() >= 255),
+                         "max_abs_err_sampled": err, "tilde_tau": st["tilde_tau"],
+                         "omega_kept": kept, "spectrum_s": spec_s, "spectrum_residual": res,
+                         "lambda_omega": float(abs(lam[-1])), "lambda_2": float(abs(lam[1]))})
+            print(f"[caltau] {name} {policy}: {1e3 * dt:.1f} ms, tau mean {t.mean():.1f} max "
+                  f"{t.max()}, err {err:.2e} (spectrum {spec_s:.1f} s, kept {kept})",
+                  file=sys.stderr, flush=True)
+        g.free()
+    head = [r for r in rows if r["graph"] == "king_grid_10000" and r["policy"] == "caltau"][0]
+    line = {
+        "metric": "all-edge SC edges/sec with CalTau truncation",
+        "value": head["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "CalTau (omega=128, device Lanczos) vs the lambda*-bound on "
+                               "king grids (TGT, eps=1e-2) and ba_100k (TGT+, eps=1e-3); "
+                               "value = king_grid_10000 with CalTau", "rows": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -534,6 +597,9 @@ def main():
         return
     if a.form == "eps":
         eps_form(a)
+        return
+    if a.form == "caltau":
+        caltau_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc
