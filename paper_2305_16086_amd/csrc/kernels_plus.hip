@@ -6,6 +6,7 @@
 // the thread schedule.
 #include "philox.hpp"
 #include "sc_internal.hpp"
+#include "accumulate.hpp"
 
 #include <cfloat>
 #include <climits>
@@ -83,10 +84,21 @@ __device__ inline void list_last(const double (&lv)[kMaxGamma], const int (&li)[
 //     (Algorithm 3 lines 3-5, safe reading), extremes over N(s).
 // Chunk p of column c: pmx/pmn[c*kColParts + p], lists pv/pi[(p*B + c)*gamma + r].
 
+// Workgroups after col_blocks carry the accumulation of the step held in Y
+// (acc; Algorithm 2 lines 10-11), saving a launch.
 template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part, int nparts,
                                                      const T* __restrict__ Y,
-                                                     T* __restrict__ pmx, T* __restrict__ pmn) {
+                                                     T* __restrict__ pmx, T* __restrict__ pmn,
+                                                     int col_blocks, AccJob acc,
+                                                     const int32_t* __restrict__ slot_row,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ inv_deg_d) {
+  if (static_cast<int>(blockIdx.x) >= col_blocks) {
+    const int k = acc.kbeg + (blockIdx.x - col_blocks) * kThreads + threadIdx.x;
+    accumulate_half<T, B>(acc, slot_row, col, inv_deg_d, Y, k);
+    return;
+  }
   constexpr int G = 64 / B;
   __shared__ T smx[kThreads], smn[kThreads];
   const int lane = threadIdx.x & 63;
@@ -768,7 +780,7 @@ __global__ void k_walk_finish(int kbeg, int kend, const long long* __restrict__ 
 
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
-                           ColStats* cs, void* scratch, hipStream_t st) {
+                           ColStats* cs, void* scratch, hipStream_t st, const AccJob* acc) {
   int ncols = B;
   if (s0 + ncols > g.n) ncols = g.n - s0;
   if (ncols <= 0) return hipSuccess;
@@ -787,8 +799,13 @@ hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const
   int* act = reinterpret_cast<int*>(pmn + cells);             // [64][kColParts]
   int* nact = act + cells;                                     // [64]
   T* thr = reinterpret_cast<T*>(nact + 64);                    // [64]
-  SC_DISPATCH_B(B, (k_colmax<T, kB><<<waves / kWavesPerBlock, kThreads, 0, st>>>(
-                        g.n, rows, nparts, Y, pmx, pmn)));
+  const int col_blocks = waves / kWavesPerBlock;
+  const AccJob job = acc ? *acc : AccJob{};
+  const int acc_blocks =
+      job.gacc && job.kend > job.kbeg ? static_cast<int>(grid_for(job.kend - job.kbeg, kThreads)) : 0;
+  SC_DISPATCH_B(B, (k_colmax<T, kB><<<col_blocks + acc_blocks, kThreads, 0, st>>>(
+                        g.n, rows, nparts, Y, pmx, pmn, col_blocks, job, g.slot_row, g.col,
+                        g.inv_deg_d)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64 * kThreshWaves, 0, st>>>(
@@ -863,9 +880,9 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
 }
 
 template hipError_t launch_colstats<float>(const DeviceGraph&, int, int, int, const float*,
-                                           ColStats*, void*, hipStream_t);
+                                           ColStats*, void*, hipStream_t, const AccJob*);
 template hipError_t launch_colstats<double>(const DeviceGraph&, int, int, int, const double*,
-                                            ColStats*, void*, hipStream_t);
+                                            ColStats*, void*, hipStream_t, const AccJob*);
 template hipError_t launch_walk_counts<float>(const DeviceGraph&, int, int, int, int, int, int,
                                               double, int64_t, const float*, const ColStats*,
                                               const int32_t*, int64_t*, hipStream_t);

@@ -9,6 +9,7 @@
 // kGiant neighbours is cut into workgroup chunks whose partial sums a fix-up
 // pass adds in chunk order.
 #include "sc_internal.hpp"
+#include "accumulate.hpp"
 #include <hip/hip_ext.h>
 #include "tau.hpp"
 
@@ -166,21 +167,18 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t n, int64_t ld, const doubl
 // u in N(s_set + c) in buffer `buf`; waves [B, 2B) clear what block s_clear
 // marked in the other buffer.  Each buffer only ever holds one block's bits,
 // so clearing may zero whole words.
-__global__ void k_mask_update(int n, int s_set, int s_clear, int B, int buf, int64_t mwords,
-                              int64_t awords, const int32_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, unsigned long long* mask,
-                              unsigned* anymask) {
-  const int w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (w >= 2 * B) return;
-  const bool set = w < B;
-  const int c = set ? w : w - B;
-  const int sb = set ? s_set : s_clear;
+__device__ inline void mask_update_wave(int w, int lane, int n, const MaskJob& mj,
+                                        const int32_t* __restrict__ rowptr,
+                                        const int32_t* __restrict__ col) {
+  if (w >= 2 * mj.B) return;
+  const bool set = w < mj.B;
+  const int c = set ? w : w - mj.B;
+  const int sb = set ? mj.s_set : mj.s_clear;
   const int s = sb + c;
   if (sb < 0 || s >= n) return;
-  const int b = set ? buf : 1 - buf;
-  unsigned long long* mk = mask + static_cast<size_t>(b) * mwords;
-  unsigned* am = anymask + static_cast<size_t>(b) * awords;
+  const int b = set ? mj.buf : 1 - mj.buf;
+  unsigned long long* mk = mj.mask + static_cast<size_t>(b) * mj.mwords;
+  unsigned* am = mj.anymask + static_cast<size_t>(b) * mj.awords;
   const unsigned long long bit = 1ull << c;
   for (int k = rowptr[s] + lane; k < rowptr[s + 1]; k += 64) {
     const int u = col[k];
@@ -192,6 +190,12 @@ __global__ void k_mask_update(int n, int s_set, int s_clear, int B, int buf, int
       am[u >> 5] = 0u;
     }
   }
+}
+
+__global__ void k_mask_update(int n, MaskJob mj, const int32_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col) {
+  mask_update_wave(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6), threadIdx.x & 63, n, mj,
+                   rowptr, col);
 }
 
 // ------------------------------------------------------------------ wave helpers
@@ -235,18 +239,16 @@ struct RowArgs {
   AccJob acc;
   // rows known to be zero in Yp (nz[u] == 0, B = 64 only)
   const uint8_t* nz;
+  // the next block's mask update (workgroups after the accumulation)
+  int acc_blocks;
+  MaskJob mj;
+  int n;
 };
 
 // gacc[k] += (Y[s][c] - Y[j][c]) / d_s for slot k = (s -> j), l <= tau_k (Eq. 9)
 template <typename T, int B>
 __device__ inline void accumulate_slot(const RowArgs<T>& a, const T* Y, int k) {
-  if (k >= a.acc.kend || a.acc.ell > a.acc.tau[k]) return;
-  const int s = a.slot_row[k];
-  const int c = s - a.acc.s0;
-  const int j = a.col[k];
-  const double pss = static_cast<double>(Y[static_cast<size_t>(s) * B + c]);
-  const double pjs = static_cast<double>(Y[static_cast<size_t>(j) * B + c]);
-  a.acc.gacc[k] += (pss - pjs) * a.inv_deg_d[s];
+  accumulate_half<T, B>(a.acc, a.slot_row, a.col, a.inv_deg_d, Y, k);
 }
 
 // Sum over the 64-slot pieces first, first + step, ... of [beg, end) of the
@@ -543,8 +545,13 @@ template <typename T, int B, bool kSkip>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_propagate(RowArgs<T> a, const T* __restrict__ Yp,
                                                         T* __restrict__ Yn) {
   if (static_cast<int>(blockIdx.x) >= a.row_blocks) {
-    const int k = a.acc.kbeg + (blockIdx.x - a.row_blocks) * kThreads + threadIdx.x;
-    accumulate_slot<T, B>(a, Yp, k);
+    const int t = blockIdx.x - a.row_blocks;
+    if (t < a.acc_blocks) {
+      accumulate_slot<T, B>(a, Yp, a.acc.kbeg + t * kThreads + threadIdx.x);
+    } else {
+      mask_update_wave((t - a.acc_blocks) * kWavesPerBlock + (threadIdx.x >> 6),
+                       threadIdx.x & 63, a.n, a.mj, a.rowptr, a.col);
+    }
     return;
   }
   const int lane = threadIdx.x & 63;
@@ -699,12 +706,24 @@ hipError_t launch_ritz(int64_t n, int64_t ld, const double* V, int steps, const 
   return hipGetLastError();
 }
 
+MaskJob mask_job(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
+                 unsigned long long* mask, unsigned* anymask) {
+  MaskJob mj;
+  mj.s_set = s_set;
+  mj.s_clear = s_clear;
+  mj.B = B;
+  mj.buf = buf;
+  mj.mwords = g.n;
+  mj.awords = (g.n + 31) / 32;
+  mj.mask = mask;
+  mj.anymask = anymask;
+  return mj;
+}
+
 hipError_t launch_mask_update(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
                               unsigned long long* mask, unsigned* anymask, hipStream_t st) {
-  const int64_t mwords = g.n;
-  const int64_t awords = (g.n + 31) / 32;
   k_mask_update<<<grid_for(2 * B, kWavesPerBlock), kThreads, 0, st>>>(
-      g.n, s_set, s_clear, B, buf, mwords, awords, g.rowptr, g.col, mask, anymask);
+      g.n, mask_job(g, s_set, s_clear, B, buf, mask, anymask), g.rowptr, g.col);
   return hipGetLastError();
 }
 
@@ -741,6 +760,9 @@ RowArgs<T> row_args(const DeviceGraph& g, int B, T* partials, const AccJob& acc)
   a.inv_deg_d = g.inv_deg_d;
   a.acc = acc;
   a.nz = nullptr;
+  a.acc_blocks = 0;
+  a.mj = MaskJob{};
+  a.n = g.n;
   return a;
 }
 
@@ -771,9 +793,15 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
                                  const AccJob& acc, hipStream_t st, const uint8_t* nz,
-                                 hipEvent_t ev_start, hipEvent_t ev_stop) {
+                                 hipEvent_t ev_start, hipEvent_t ev_stop, const MaskJob* mj) {
   RowArgs<T> a = row_args<T>(g, B, partials, acc);
-  const int blocks = a.row_blocks + acc_blocks(acc);
+  a.acc_blocks = acc_blocks(acc);
+  int mask_blocks = 0;
+  if (mj && mj->B > 0) {
+    a.mj = *mj;
+    mask_blocks = static_cast<int>(grid_for(2 * mj->B, kWavesPerBlock));
+  }
+  const int blocks = a.row_blocks + a.acc_blocks + mask_blocks;
   if (B == 64 && nz) {
     a.nz = nz;
     hipExtLaunchKernelGGL(k_propagate<T, 64, true>, dim3(blocks), dim3(kThreads), 0, st,
@@ -844,10 +872,11 @@ template hipError_t launch_twohop<double>(const DeviceGraph&, int, const unsigne
                                           const unsigned*, double*, double*, uint8_t*, hipStream_t);
 template hipError_t launch_propagate_rows<float>(const DeviceGraph&, int, const float*, float*,
                                                 float*, const AccJob&, hipStream_t, const uint8_t*,
-                                                hipEvent_t, hipEvent_t);
+                                                hipEvent_t, hipEvent_t, const MaskJob*);
 template hipError_t launch_propagate_rows<double>(const DeviceGraph&, int, const double*, double*,
                                                  double*, const AccJob&, hipStream_t,
-                                                 const uint8_t*, hipEvent_t, hipEvent_t);
+                                                 const uint8_t*, hipEvent_t, hipEvent_t,
+                                                 const MaskJob*);
 template hipError_t launch_fixup<float>(const DeviceGraph&, int, const float*, float*, hipStream_t);
 template hipError_t launch_fixup<double>(const DeviceGraph&, int, const double*, double*, hipStream_t);
 template hipError_t launch_propagate<float>(const DeviceGraph&, int, const float*, float*,

@@ -429,17 +429,18 @@ hipError_t lanczos_start(const sc::DeviceGraph& dg, const int32_t* deg_host, dou
 // Eigenvalues of the symmetric tridiagonal matrix (diagonal d[0..k), off-diagonal
 // e[0..k-1)) by implicit QL iterations with Wilkinson-type shifts (Wilkinson and
 // Reinsch; Golub and Van Loan, implicit symmetric tridiagonal QR).  d receives
-// the eigenvalues (unordered).  z (k x k row-major), if given, receives the
-// eigenvectors as columns; zlast, if given, their last components only.
+// the eigenvalues (unordered).  zt (k x k), if given, receives the eigenvectors
+// as rows (zt[c * k + i] = component i of the vector of d[c]); zlast, if given,
+// their last components only.
 // Returns false if an eigenvalue needs more than 60 iterations.
-bool tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<double>* z,
+bool tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<double>* zt,
                    std::vector<double>* zlast) {
   const int k = static_cast<int>(d.size());
   e.resize(k, 0.0);
   e[k - 1] = 0.0;
-  if (z) {
-    z->assign(static_cast<size_t>(k) * k, 0.0);
-    for (int i = 0; i < k; ++i) (*z)[static_cast<size_t>(i) * k + i] = 1.0;
+  if (zt) {
+    zt->assign(static_cast<size_t>(k) * k, 0.0);
+    for (int i = 0; i < k; ++i) (*zt)[static_cast<size_t>(i) * k + i] = 1.0;
   }
   if (zlast) {
     zlast->assign(k, 0.0);
@@ -477,12 +478,13 @@ bool tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<do
         p = sn * r;
         d[i + 1] = g + p;
         g = cs * r - b;
-        if (z) {
+        if (zt) {   // rotate vectors i and i + 1 (two contiguous rows)
+          double* ri = zt->data() + static_cast<size_t>(i) * k;
+          double* rj = ri + k;
           for (int q = 0; q < k; ++q) {
-            double* row = z->data() + static_cast<size_t>(q) * k;
-            const double t = row[i + 1];
-            row[i + 1] = sn * row[i] + cs * t;
-            row[i] = cs * row[i] - sn * t;
+            const double t = rj[q];
+            rj[q] = sn * ri[q] + cs * t;
+            ri[q] = cs * ri[q] - sn * t;
           }
         }
         if (zlast) {
@@ -694,7 +696,7 @@ int sc::lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipSt
   int p = 0;
   double wres = 0.0;
   while (p < want && p < steps) {
-    const double r = exact ? 0.0 : std::fabs(b_last * Z[static_cast<size_t>(steps - 1) * steps + idx[p]]);
+    const double r = exact ? 0.0 : std::fabs(b_last * Z[static_cast<size_t>(idx[p]) * steps + steps - 1]);
     if (r > tol) break;
     wres = std::max(wres, r);
     ++p;
@@ -707,7 +709,7 @@ int sc::lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipSt
   const int p32 = (p + kRitzCols - 1) / kRitzCols * kRitzCols;
   std::vector<double> Y(static_cast<size_t>(steps) * p32, 0.0);
   for (int i = 0; i < steps; ++i)
-    for (int c = 0; c < p; ++c) Y[static_cast<size_t>(i) * p32 + c] = Z[static_cast<size_t>(i) * steps + idx[c]];
+    for (int c = 0; c < p; ++c) Y[static_cast<size_t>(i) * p32 + c] = Z[static_cast<size_t>(idx[c]) * steps + i];
   std::vector<double> lam(om);
   lam[0] = 1.0;
   for (int c = 0; c < p; ++c) lam[1 + c] = th[idx[c]];
@@ -1093,19 +1095,26 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     if (b >= 2) HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[3 + pair], 0));
     R.st = st;
     R.po = 2 * pair;
-    rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc);
+    rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc, b + 1 < nblocks ? s0 + B : -1);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(g->pipe_ev[1 + pair], st));
     HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[1 + pair], 0));
     R.st = sb;
-    rc = R.flush_acc();
-    if (rc) return rc;
+    // the last step's accumulation rides on the candidate summary's first
+    // launch when there is one (same state, same stream)
+    const bool fuse_acc = plus && tmax > tilde && tilde >= 2;
+    if (!fuse_acc) {
+      rc = R.flush_acc();
+      if (rc) return rc;
+    }
     if (plus && tmax > tilde) {
       if (tilde < 2) {
         rc = R.init_low(s0, tilde);
         if (rc) return rc;
       }
-      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, sb));
+      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, sb,
+                                     fuse_acc ? &R.pending_acc : nullptr));
+      R.pending_acc = sc::AccJob{};
       HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
                                         R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, sb));
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),

@@ -229,19 +229,26 @@ struct Runner {
 
   // traverse the block from l = 2 up to l = lend (l = 0, 1 are closed form);
   // the accumulation of step l rides on the launch of step l + 1, the last one
-  // stays pending (flush_acc or a fused consumer launches it)
-  int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc) {
+  // stays pending (flush_acc or a fused consumer launches it).  With next_s0 >= 0
+  // the first dense step also sets the masks of block next_s0 and clears this
+  // block's (the two-hop step, the only reader, is done by then).
+  int traverse(int s0, int kbeg, int kend, int lend, bool acc, double* gacc, int next_s0 = -1) {
     pending_acc = AccJob{};
     if (lend < 2) return SC_OK;
-    const int buf = g->mask_pending_s0 >= 0 ? 1 - g->mask_pending_buf : 0;
-    if (g->mask_pending_s0 >= 0 && g->mask_pending_B != B) {
-      int rc0 = flush_masks();
-      if (rc0) return rc0;
+    int buf;
+    if (g->mask_pending_s0 == s0 && g->mask_pending_B == B) {
+      buf = g->mask_pending_buf;   // a buffer only ever holds one block's bits: these are s0's
+    } else {
+      buf = g->mask_pending_s0 >= 0 ? 1 - g->mask_pending_buf : 0;
+      if (g->mask_pending_s0 >= 0 && g->mask_pending_B != B) {
+        int rc0 = flush_masks();
+        if (rc0) return rc0;
+      }
+      HIP_TRY(launch_mask_update(g->d, s0, g->mask_pending_s0, B, buf, g->mask, g->anymask, st));
+      g->mask_pending_s0 = s0;
+      g->mask_pending_buf = buf;
+      g->mask_pending_B = B;
     }
-    HIP_TRY(launch_mask_update(g->d, s0, g->mask_pending_s0, B, buf, g->mask, g->anymask, st));
-    g->mask_pending_s0 = s0;
-    g->mask_pending_buf = buf;
-    g->mask_pending_B = B;
     unsigned long long* mk = g->mask + static_cast<size_t>(buf) * g->d.n;
     unsigned* am = g->anymask + static_cast<size_t>(buf) * ((g->d.n + 31) / 32);
     cur = 0;
@@ -274,9 +281,16 @@ struct Runner {
         rc = event_pair(&a, &b);
         if (rc) return rc;
       }
+      MaskJob mj;
+      const bool carry = ell == 3 && next_s0 >= 0;
+      if (carry) mj = mask_job(g->d, next_s0, s0, B, 1 - buf, g->mask, g->anymask);
       // a and b (when timed) take the kernel's own start and end times
       HIP_TRY(launch_propagate_rows<T>(g->d, B, Yb(cur), Yb(1 - cur), parts(), pending_acc, st,
-                                       skip ? g->nz : nullptr, a, b));
+                                       skip ? g->nz : nullptr, a, b, carry ? &mj : nullptr));
+      if (carry) {
+        g->mask_pending_s0 = next_s0;
+        g->mask_pending_buf = 1 - buf;
+      }
       HIP_TRY(launch_fixup<T>(g->d, B, parts(), Yb(1 - cur), st));
       if (!skip) {
         ++stats.prop_launches;

@@ -51,6 +51,15 @@ struct AccJob {
   double* gacc = nullptr;
 };
 
+// Neighbour-bit update of the two-hop masks: set the bits of block s_set in
+// buffer buf, clear those of block s_clear in buffer 1 - buf (s_* < 0: none).
+struct MaskJob {
+  int s_set = -1, s_clear = -1, B = 0, buf = 0;
+  int64_t mwords = 0, awords = 0;
+  unsigned long long* mask = nullptr;
+  unsigned* anymask = nullptr;
+};
+
 struct DeviceGraph {
   int32_t n = 0;
   int64_t m = 0;                 // input edges (halves 0..2m-1)
@@ -164,10 +173,14 @@ hipError_t launch_twohop(const DeviceGraph& g, int B, const unsigned long long* 
 // and nz, neighbours u with nz[u] == 0 are not gathered (their rows of Yp are
 // exact zeros, so every sum is unchanged).  Non-null ev_start / ev_stop take
 // the start and end times of the row-gather kernel itself.
+// mj (may be null): a mask update carried by extra workgroups of the same launch.
 template <typename T>
 hipError_t launch_propagate_rows(const DeviceGraph& g, int B, const T* Yp, T* Yn, T* partials,
                                  const AccJob& acc, hipStream_t st, const uint8_t* nz = nullptr,
-                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                                 const MaskJob* mj = nullptr);
+MaskJob mask_job(const DeviceGraph& g, int s_set, int s_clear, int B, int buf,
+                 unsigned long long* mask, unsigned* anymask);
 template <typename T>
 hipError_t launch_fixup(const DeviceGraph& g, int B, const T* partials, T* Y, hipStream_t st);
 
@@ -190,7 +203,8 @@ constexpr size_t kColScratchBytes =
     64 * (sizeof(int) + sizeof(double));
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
-                           ColStats* cs, void* scratch, hipStream_t st);
+                           ColStats* cs, void* scratch, hipStream_t st,
+                           const AccJob* acc = nullptr);
 
 // n_r per slot (Eq. 13 with chi of Eq. 17 / Eq. 15); 0 where tau_k <= tilde.
 template <typename T>
