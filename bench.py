@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=48)
-    p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau"],
+    p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau",
+                                      "params"],
                    default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
                         "persistent launch against one graph at a time; learned: the "
@@ -581,6 +582,65 @@ def caltau_form(a):
     print(json.dumps(line), flush=True)
 
 
+def params_form(a):
+    """The parameter study of Section 5.4 (Figure 5): TGT+ time and walk count
+    against omega (CalTau pairs, Algorithm 1) in {2, 8, 32, 128} with gamma = 10,
+    and against gamma (Algorithm 3 candidates) in {0, 2, 5, 10, 16} with the
+    lambda*-bound.  omega: the device spectrum at omega = 128, then its first
+    omega pairs loaded with sc_set_spectrum.  Graphs: king grid n = 2,500 and the
+    HepPh-shaped BA stand-in at eps = 0.05 (the paper's setting), and ba_100k at
+    eps = 1e-3 for gamma."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    cases = (("king_grid_2500", gg.king_grid(2500), 0.05, True),
+             ("hepph-shaped", gg.barabasi_albert(34_401, 12, SEED), 0.05, True),
+             ("ba_100k", gg.workload("ba_100k", SEED), 1e-3, False))
+    for name, graph, eps, do_omega in cases:
+        n, u, v = graph
+        m = len(u)
+        g = sc.sc_build_graph(n, u, v)
+        out = torch.empty(m, dtype=torch.float64, device=dev)
+
+        def point(label, value, flags, gamma):
+            o = sc.sc_default_options(method=sc.SC_TGT_PLUS, precision=0, block=BLOCK,
+                                      flags=flags, gamma=gamma, stream=stream.cuda_stream)
+            dt, st = timed_calls(sc, g, eps, o, out, a.steps, a.warmup)
+            rows.append({"graph": name, "n": n, "m": m, "eps": eps, label: value,
+                         "gamma": gamma, "ms": 1e3 * dt, "walks": st["walks"],
+                         "L_used": st["L_used"], "tilde_tau": st["tilde_tau"]})
+            print(f"[params] {name} {label}={value} gamma={gamma}: {1e3 * dt:.1f} ms, "
+                  f"walks {st['walks']}, L {st['L_used']}, tilde {st['tilde_tau']}",
+                  file=sys.stderr, flush=True)
+
+        if do_omega:
+            kept, _ = sc.sc_compute_spectrum(g, 128, 2048, 1e-8)
+            lam, phi = sc.sc_get_spectrum(g)
+            for omega in (2, 8, 32, 128):
+                w = min(omega, kept)
+                sc.sc_set_spectrum(g, lam[:w], phi[:, :w])
+                point("omega", w, sc.SC_TAU_SPECTRAL, 10)
+        for gamma in (0, 2, 5, 10, 16):
+            point("gamma_sweep", gamma, 0, gamma)
+        g.free()
+    head = [r for r in rows if r["graph"] == "ba_100k" and r.get("gamma_sweep") == 10][0]
+    line = {
+        "metric": "TGT+ time across omega and gamma (Section 5.4)",
+        "value": m / (head["ms"] * 1e-3), "unit": "edges/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "omega and gamma sweeps (value: ba_100k, gamma = 10)",
+                   "rows": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -600,6 +660,9 @@ def main():
         return
     if a.form == "caltau":
         caltau_form(a)
+        return
+    if a.form == "params":
+        params_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc

@@ -422,14 +422,28 @@ __global__ __launch_bounds__(64) void k_colmerge(int n, int s0, int gamma,
   }
   double best = -DBL_MAX;
   if (gamma > 0) {
-    for (int p = 0; p < cnt * cnt; p += 64) {
+    // the cnt (cnt - 1) / 2 unordered candidate pairs, one per lane; each test
+    // searches the shorter of the two neighbour lists (adjacency is symmetric)
+    const int npairs = cnt * (cnt - 1) / 2;
+    for (int p = 0; p < npairs; p += 64) {
       const int q = p + lane;
-      const int a = q / cnt, b = q % cnt;
-      const int ia = __shfl(top_i, a < 64 ? a : 0, 64);
-      const int ib = __shfl(top_i, b < 64 ? b : 0, 64);
-      const double va = __shfl(top_v, a < 64 ? a : 0, 64);
-      const double vb = __shfl(top_v, b < 64 ? b : 0, 64);
-      if (q < cnt * cnt && a < b && adjacent(rowptr, col, ia, ib)) best = fmax(best, va + vb);
+      int a = 0, b = 1, rem = q;
+      while (a < cnt - 1 && rem >= cnt - 1 - a) {   // q -> (a, b), a < b, row by row
+        rem -= cnt - 1 - a;
+        ++a;
+      }
+      b = a + 1 + rem;
+      const bool on = q < npairs;
+      const int ia = __shfl(top_i, on ? a : 0, 64);
+      const int ib = __shfl(top_i, on && b < 64 ? b : 0, 64);
+      const double va = __shfl(top_v, on ? a : 0, 64);
+      const double vb = __shfl(top_v, on && b < 64 ? b : 0, 64);
+      if (on) {
+        const int da = rowptr[ia + 1] - rowptr[ia];
+        const int db = rowptr[ib + 1] - rowptr[ib];
+        const bool adj = da <= db ? adjacent(rowptr, col, ia, ib) : adjacent(rowptr, col, ib, ia);
+        if (adj) best = fmax(best, va + vb);
+      }
     }
   }
   double nmx = -DBL_MAX, nmn = DBL_MAX;
