@@ -164,3 +164,52 @@ def test_spectrum_errors_and_round_trip(sc):
         sc.sc_batch_all_edges(b, 1e-2, None, sc.sc_default_options(flags=sc.SC_TAU_SPECTRAL))
     assert e.value.code == sc.SC_ENOTIMPL
     b.free()
+
+
+@pytest.mark.parametrize("name", ["petersen", "K5", "tri_pendant"])
+def test_caltau_tiny_graphs_given_spectrum(sc, name):
+    # repeated eigenvalues (Petersen 1/3 x5, -2/3 x4; K5 -1/4 x4): the caller's pairs
+    graph = {"petersen": gg.petersen_graph(), "K5": gg.complete_graph(5),
+             "tri_pendant": gg.triangle_pendant()}[name]
+    n, u, v = graph
+    exact = ex.sc_pinv(n, u, v)
+    g = sc.sc_build_graph(n, u, v)
+    for omega in (2, 3, n):
+        lam, phi = ct.top_spectrum(n, u, v, omega)
+        sc.sc_set_spectrum(g, lam, phi)
+        for eps in (1e-2, 1e-4):
+            out, st, tau, _, _ = run(sc, g, eps, method=sc.SC_TGT, precision=1,
+                                     flags=sc.SC_TAU_SPECTRAL)
+            want = ct.caltau(n, u, v, eps, lam, phi, max_L=255)
+            assert np.all(np.abs(tau.astype(np.int64) - want) <= 2)
+            assert np.abs(out - exact).max() <= eps
+    g.free()
+
+
+def test_compute_spectrum_clamps_omega_to_n(sc):
+    n, u, v = gg.random_small_connected(40, 90, 7)
+    g = sc.sc_build_graph(n, u, v)
+    kept, res = sc.sc_compute_spectrum(g, 128, 0, 1e-10)
+    lam, phi = sc.sc_get_spectrum(g)
+    g.free()
+    assert kept <= n and phi.shape == (n, kept)
+    ref, _ = ct.top_spectrum(n, u, v, kept)
+    np.testing.assert_allclose(lam, ref, atol=1e-9, rtol=0)
+
+
+def test_caltau_with_max_L_cap_tgt_plus(sc):
+    n, u, v = gg.king_grid(400)
+    lam, phi = ct.top_spectrum(n, u, v, 6)
+    g = sc.sc_build_graph(n, u, v)
+    sc.sc_set_spectrum(g, lam, phi)
+    out, st, tau, tt, nr = run(sc, g, 0.2, method=sc.SC_TGT_PLUS, precision=1, max_L=9,
+                               tilde_tau=3, seed=11, flags=sc.SC_TAU_SPECTRAL)
+    g.free()
+    want = ct.caltau(n, u, v, 0.1, lam, phi, max_L=9)
+    assert tau.max() <= 9 and np.mean(tau == want) >= 0.99
+    m = len(u)
+    srcs = np.unique(np.concatenate([u[::97], v[::97]]))   # both ends of some edges
+    _, _, ref = otgt.tgt_plus_replay(otgt.Graph(n, u, v), tau, tt, nr[:m], nr[m:], seed=11,
+                                     sources=srcs)
+    both = np.isin(u, srcs) & np.isin(v, srcs)
+    np.testing.assert_allclose(out[both], ref[both], atol=FP64_TOL, rtol=0)
