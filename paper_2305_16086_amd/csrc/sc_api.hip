@@ -546,6 +546,7 @@ int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipS
     dev_free(h);
     dev_free(sid);
   };
+  const ScopeExit<decltype(cleanup)> guard{cleanup};   // also on early error returns
   hipError_t e = dev_alloc(&V, static_cast<size_t>(kmax + 2) * ld);
   if (e == hipSuccess) e = dev_alloc(&w, n);
   if (e == hipSuccess) e = dev_alloc(&h, kmax + 2);
@@ -628,6 +629,7 @@ int sc::lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipSt
     dev_free(sid);
     dev_free(Yd);
   };
+  const ScopeExit<decltype(cleanup)> guard{cleanup};   // also on early error returns
   hipError_t e = dev_alloc(&V, static_cast<size_t>(kmax + 2) * ld);
   if (e == hipSuccess) e = dev_alloc(&w, n);
   if (e == hipSuccess) e = dev_alloc(&h, kmax + 2);

@@ -25,6 +25,13 @@ void dev_free(P*& p) {
   p = nullptr;
 }
 
+// runs f when the scope ends (releases buffers on every return path)
+template <typename F>
+struct ScopeExit {
+  F& f;
+  ~ScopeExit() { f(); }
+};
+
 }  // namespace sc
 
 #define HIP_TRY(expr)                                                              \
