@@ -50,7 +50,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sources", type=int, default=48)
+    p.add_argument("--cpu-sources", type=int, default=1500,
+                   help="sources in the CPU-baseline sample (about 10-15 s of CPU work)")
     p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau",
                                       "params"],
                    default="plain",
@@ -78,9 +79,11 @@ def cpu_baseline(graph, tau, tilde, nr, nsrc):
     rng = np.random.default_rng(7)
     srcs = rng.choice(n, size=nsrc, replace=False)
     G = otgt.Graph(n, u, v)
-    t0 = time.perf_counter()
-    otgt.tgt_plus_replay(G, tau, tilde, nr[:m], nr[m:], seed=0x5C5C, sources=srcs)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):   # one core, as reported
+        t0 = time.perf_counter()
+        otgt.tgt_plus_replay(G, tau, tilde, nr[:m], nr[m:], seed=0x5C5C, sources=srcs)
+        dt = time.perf_counter() - t0
     full = dt * n / nsrc
     return {"value": m / full, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"TGT+ replay (float64, scipy sparse, single thread) from {nsrc} random "
