@@ -616,20 +616,6 @@ __device__ inline void slot_walks(int k, int lane, int s0, int tilde, unsigned k
   if (lane == 0) gacc[k] += acc / static_cast<double>(n_r);
 }
 
-// One wave per slot (the walk tail without chunk scratch).
-template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_walks(
-    int kbeg, int kend, int s0, int tilde, unsigned k0, unsigned k1,
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ slot_row, const double* __restrict__ inv_deg,
-    const T* __restrict__ Y, const int32_t* __restrict__ tau, const long long* __restrict__ nr,
-    double* __restrict__ gacc) {
-  const int lane = threadIdx.x & 63;
-  const int k = kbeg + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (k >= kend) return;
-  slot_walks<T, B>(k, lane, s0, tilde, k0, k1, rowptr, col, slot_row, inv_deg, Y, tau, nr, gacc);
-}
-
 // ---------------------------------------------------------------- flattened walks
 // The walk pairs of a block's half-edges are cut into chunks of 64 pairs
 // (chunk_off: exclusive prefix of ceil(n_r / 64) over the block's slots, one
@@ -873,13 +859,7 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
   const long long* nr = reinterpret_cast<const long long*>(nr_slot);
   long long* off = reinterpret_cast<long long*>(ws.chunk_off);
   long long* ctl = reinterpret_cast<long long*>(ws.ctl);
-  const bool flat = ws.chunk_off && ws.part && ws.ctl;
-  if (!flat) {   // no chunk scratch: one wave per slot
-    SC_DISPATCH_B(B, (k_walks<T, kB><<<grid_for(kend - kbeg, kWavesPerBlock), kThreads, 0, st>>>(
-                          kbeg, kend, s0, tilde, k0, k1, g.rowptr, g.col, g.slot_row,
-                          g.inv_deg_d, Y, tau_slot, nr, gacc)));
-    return hipGetLastError();
-  }
+  if (!ws.chunk_off || !ws.part || !ws.ctl) return hipErrorInvalidValue;   // scratch required
   k_walk_scan<<<1, kScanThreads, 0, st>>>(kbeg, kend, nr, off, ws.capacity, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -225,7 +225,8 @@ struct WalkScratch {
   int64_t* ctl = nullptr;         // [2]
 };
 
-// Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots.
+// Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots (ws must hold
+// the chunk buffers; blocks whose chunks do not fit walk one slot per wave).
 template <typename T>
 hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                         uint64_t seed, const T* Y, const int32_t* tau_slot,
