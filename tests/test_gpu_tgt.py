@@ -295,3 +295,52 @@ def test_giant_and_heavy_rows(sc, precision, block):
     out, _, tau, _, _ = run(sc, graph, 0.1, 5, method=sc.SC_TGT, precision=precision, block=block)
     ref = otgt.truncated_sc(otgt.Graph(*graph), tau)
     np.testing.assert_allclose(out, ref, atol=FP64_TOL if precision else FP32_TOL, rtol=0)
+
+
+def two_density_graph(seed=3):
+    """Nodes 0-191: G(n, p = 0.8); nodes 192-791: G(n, p) of mean degree 24;
+    2,400 random edges join nodes 128-191 to the sparse part.  At eps = 0.05
+    the lambda*-bound gives tau = 1 on every edge of nodes 0-127 (two whole
+    source blocks of 64 with no traversal) and tau = 7-11 elsewhere."""
+    rng = np.random.default_rng(seed)
+    nd, ns = 192, 600
+    iu = np.triu_indices(nd, 1)
+    keep = rng.random(len(iu[0])) < 0.8
+    _, u2, v2 = gg.gnp_connected(ns, 24.0, seed)
+    a = rng.integers(128, nd, size=2400)
+    b = rng.integers(nd, nd + ns, size=2400)
+    u = np.concatenate([iu[0][keep], u2 + nd, a])
+    v = np.concatenate([iu[1][keep], v2 + nd, b])
+    return (nd + ns,) + gg.canonical_edges(nd + ns, u, v)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_blocks_without_traversal_are_skipped_correctly(sc, precision):
+    graph = two_density_graph()
+    n, u, v = graph
+    m = len(u)
+    G = otgt.Graph(n, u, v)
+    tol = FP64_TOL if precision else FP32_TOL
+    eps = 0.05
+    out, st, tau, _, _ = run(sc, graph, eps, 0, method=sc.SC_TGT, precision=precision)
+    d = ex.degree_vector(n, u, v)
+    want_tau = otgt.tau_lambda_bound(d[u], d[v], eps, ex.lambda_star(n, u, v))
+    np.testing.assert_array_equal(tau, want_tau)
+    low = (u < 128) & (v < 128)
+    assert np.all(tau[(u < 128) | (v < 128)] == 1) and tau.max() >= 7 and low.sum() > 5000
+    np.testing.assert_allclose(out, otgt.truncated_sc(G, tau), atol=tol, rtol=0)
+    # TGT+ at 2 eps (it truncates at eps / 2, so tau is the same): with
+    # tilde = 2 the first two blocks have neither traversal nor walks (replayed
+    # on sources from both kinds of block); with tilde = 0 they have walks only
+    # (replayed on sources of the first block: their walks have one step)
+    cases = {2: np.concatenate([np.arange(0, 6), np.arange(130, 136), np.arange(300, 306)]),
+             0: np.arange(0, 8)}
+    for tilde, srcs in cases.items():
+        both = np.isin(u, srcs) & np.isin(v, srcs)
+        assert both[low].sum() > 0 and (tilde == 0 or both[~low].sum() > 0)
+        out, st, tau2, tt, nr = run(sc, graph, 2 * eps, 0, method=sc.SC_TGT_PLUS,
+                                    precision=precision, tilde_tau=tilde, seed=31)
+        np.testing.assert_array_equal(tau2, tau)
+        assert st["tilde_tau"] == tilde
+        _, _, ref = otgt.tgt_plus_replay(G, tau, tt, nr[:m], nr[m:], seed=31, sources=srcs)
+        np.testing.assert_allclose(out[both], ref[both], atol=tol, rtol=0)
