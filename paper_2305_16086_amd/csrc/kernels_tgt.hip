@@ -42,19 +42,31 @@ __global__ void k_gacc_init(int64_t nslots, const int32_t* __restrict__ slot_row
 }
 
 // ------------------------------------------------------------------ truncation lengths
-__global__ void k_tau(int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                      const int32_t* __restrict__ deg, int L, double eps_tau, double lam,
-                      int max_L, int32_t* __restrict__ tau_slot, int32_t* __restrict__ tau_row) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
+// One wave per row: the lanes stride over the row's slots (hub rows too) and a
+// butterfly max gives the row's longest truncation.
+__global__ __launch_bounds__(kThreads) void k_tau(int n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ deg, int L,
+                                                  double eps_tau, double lam, int max_L,
+                                                  int32_t* __restrict__ tau_slot,
+                                                  int32_t* __restrict__ tau_row) {
+  const int x = blockIdx.x * kWavesPerBlock + static_cast<int>(threadIdx.x) / 64;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  if (x >= n) return;   // uniform per wave
   int tmax = 0;
   const double di = static_cast<double>(deg[x]);
-  for (int k = rowptr[x]; k < rowptr[x + 1]; ++k) {
+  const int end = rowptr[x + 1];
+  for (int k = rowptr[x] + lane; k < end; k += 64) {
     const int t = tau_of(L, di, static_cast<double>(deg[col[k]]), eps_tau, lam, max_L);
     tau_slot[k] = t;
     tmax = t > tmax ? t : tmax;
   }
-  tau_row[x] = tmax;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(tmax, off, 64);
+    tmax = o > tmax ? o : tmax;
+  }
+  if (lane == 0) tau_row[x] = tmax;
 }
 
 // ------------------------------------------------------------------ CalTau (Algorithm 1)
@@ -684,8 +696,8 @@ hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int i
 
 hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
                       int32_t* tau_slot, int32_t* tau_row, hipStream_t st) {
-  k_tau<<<grid_for(g.n, 256), 256, 0, st>>>(g.n, g.rowptr, g.col, g.deg, L, eps_tau, lam, max_L,
-                                             tau_slot, tau_row);
+  k_tau<<<grid_for(g.n, kWavesPerBlock), kThreads, 0, st>>>(g.n, g.rowptr, g.col, g.deg, L,
+                                                             eps_tau, lam, max_L, tau_slot, tau_row);
   return hipGetLastError();
 }
 
