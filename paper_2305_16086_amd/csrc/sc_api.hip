@@ -852,12 +852,12 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   const int64_t S = static_cast<int64_t>(g->rowptr_h[n]);
   const size_t yb = static_cast<size_t>(n) * B * tsize;
   if (yb > g->ybytes) {
-    for (int i = 0; i < 4; ++i) {
-      if (g->Y[i]) (void)hipFree(g->Y[i]);
-      g->Y[i] = nullptr;
+    for (auto& y : g->Y) {
+      if (y) (void)hipFree(y);
+      y = nullptr;
     }
     g->ybytes = 0;
-    for (int i = 0; i < 4; ++i) HIP_TRY(hipMalloc(&g->Y[i], yb));
+    for (auto& y : g->Y) HIP_TRY(hipMalloc(&y, yb));
     g->ybytes = yb;
   }
   if (!g->nz) {
@@ -1080,16 +1080,18 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   HIP_TRY(hipMemsetAsync(work, 0, 2 * sizeof(unsigned long long), st));
   // Block pipeline: the traversal of block b runs on the caller's stream, its
   // tail (last accumulation, candidate summary, walk counts, walks) on the
-  // tail stream, overlapping the traversal of block b+1.  Blocks alternate
-  // between two Y pairs; pair p is reused only after the tail of the block
-  // two back has finished.  Blocks touch disjoint slots of gacc and nr_slot.
+  // tail stream, overlapping the traversals of the next blocks.  Blocks cycle
+  // through kPipeDepth Y pairs; a pair is reused only after the tail of the
+  // block kPipeDepth back has finished.  Blocks touch disjoint slots of gacc
+  // and nr_slot.
   rc = sc::ensure_pipeline(g);
   if (rc) return rc;
   hipStream_t sb = g->tail_stream;
   HIP_TRY(hipEventRecord(g->pipe_ev[0], st));
   HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[0], 0));
   const auto host0 = std::chrono::steady_clock::now();
-  bool tail_recorded[2] = {false, false};
+  constexpr int D = sc::kPipeDepth;
+  bool tail_recorded[D] = {};
   for (int b = 0; b < nblocks; ++b) {
     int s0, kbeg, kend, tmax;
     block_range(b, &s0, &kbeg, &kend, &tmax);
@@ -1097,8 +1099,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     // a block whose edges all stop at tau <= 1 has only the l = 0, 1 terms,
     // which the accumulator initialisation already holds: no launch, no events
     if (lend < 2 && !(plus && tmax > tilde)) continue;
-    const int pair = b & 1;
-    if (tail_recorded[pair]) HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[3 + pair], 0));
+    const int pair = b % D;
+    if (tail_recorded[pair]) HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[1 + D + pair], 0));
     R.st = st;
     R.po = 2 * pair;
     rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc, b + 1 < nblocks ? s0 + B : -1);
@@ -1126,7 +1128,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
                                   g->tau_slot, g->nr_slot, g->gacc, g->walk, sb));
     }
-    HIP_TRY(hipEventRecord(g->pipe_ev[3 + pair], sb));
+    HIP_TRY(hipEventRecord(g->pipe_ev[1 + D + pair], sb));
     tail_recorded[pair] = true;
     R.st = st;
   }

@@ -25,6 +25,10 @@ void dev_free(P*& p) {
   p = nullptr;
 }
 
+// Source blocks in flight in the per-graph pipeline: the traversal of block b
+// reuses the Y pair of block b - kPipeDepth once that block's tail is done.
+constexpr int kPipeDepth = 3;
+
 // runs f when the scope ends (releases buffers on every return path)
 template <typename F>
 struct ScopeExit {
@@ -58,10 +62,12 @@ struct sc_graph {
   std::vector<double> spec_lam_h;
 
   // work buffers, grown on demand
-  void* Y[4] = {nullptr, nullptr, nullptr, nullptr};   // two pairs (block pipeline)
+  void* Y[2 * sc::kPipeDepth] = {};        // one ping-pong pair per block in flight
   size_t ybytes = 0;
   hipStream_t tail_stream = nullptr;   // per-block tails overlap the next traversal
-  hipEvent_t pipe_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // [0] stream joins, [1 + p] traversal of the block in pair p done,
+  // [1 + kPipeDepth + p] its tail done
+  hipEvent_t pipe_ev[1 + 2 * sc::kPipeDepth] = {};
   void* partials = nullptr;
   size_t pbytes = 0;
   unsigned long long* mask = nullptr;   // 2 x n words (two alternating buffers)
@@ -177,7 +183,7 @@ struct Runner {
   sc_stats stats{};
   size_t ev_used = 0;
   int cur = 0;            // index of the Y buffer holding the latest step
-  int po = 0;             // first buffer of the Y pair in use (0 or 2)
+  int po = 0;             // first buffer of the Y pair in use (2 * pair)
   T* rdiag = nullptr;     // optional per-slot recordings of p_l(s,s), p_l(j,s)
   T* roff = nullptr;
   int record_to = -1;     // record steps 2..record_to
