@@ -647,7 +647,7 @@ def params_form(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
     if a.form == "batch":
         batch_form(a)
