@@ -10,7 +10,8 @@
 * accuracy against the exact SC (Laplacian pseudoinverse) within eps;
 * edge cases: tiny graphs, partial blocks, rows split into chunks, all block
   widths, tilde_tau of 0 and 1, gamma = 0, duplicates, device pointers,
-  determinism and error paths.
+  determinism and error paths; source blocks skipped for having nothing to
+  traverse; 2, 3, 4 and 7 blocks around the three-deep block pipeline.
 """
 import math
 
@@ -344,3 +345,19 @@ def test_blocks_without_traversal_are_skipped_correctly(sc, precision):
         assert st["tilde_tau"] == tilde
         _, _, ref = otgt.tgt_plus_replay(G, tau, tt, nr[:m], nr[m:], seed=31, sources=srcs)
         np.testing.assert_allclose(out[both], ref[both], atol=tol, rtol=0)
+
+
+@pytest.mark.parametrize("nblocks", [2, 3, 4, 7])
+def test_tgt_plus_pipeline_depths(sc, nblocks):
+    """Source blocks cycle through three state pairs, each reused once the tail
+    of the block three back is done: graphs of 2, 3, 4 and 7 blocks (the last
+    one ragged) against the oracle's replay on every edge."""
+    n = 64 * nblocks - (17 if nblocks == 7 else 0)
+    graph = gg.barabasi_albert(n, 3, 40 + nblocks)
+    n, u, v = graph
+    m = len(u)
+    out, st, tau, tt, nr = run(sc, graph, 0.2, 7, method=sc.SC_TGT_PLUS, precision=1,
+                               tilde_tau=3, seed=2024)
+    assert st["walks"] > 0
+    _, _, ref = otgt.tgt_plus_replay(otgt.Graph(n, u, v), tau, tt, nr[:m], nr[m:], seed=2024)
+    np.testing.assert_allclose(out, ref, atol=FP64_TOL, rtol=0)
