@@ -483,7 +483,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// One wave per slot k = (s -> j) of the block.
+// One wave per slot k = (s -> j) of the block.  Three loads in flight per lane
+// keep the kernel at 32 VGPRs, which is what the dense step's six waves per
+// SIMD leave free on the other stream.
+constexpr int kWcBatch = 3;
 template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void k_walk_counts(
     int kbeg, int kend, int s0, int tilde, int gamma, double coef, long long nr_cap,
@@ -503,15 +506,15 @@ __global__ __launch_bounds__(kThreads) void k_walk_counts(
   const int j = col[k];
   double jmx = -DBL_MAX, jmn = DBL_MAX;
   const int je = rowptr[j + 1];
-  for (int kb = rowptr[j] + lane; kb < je; kb += 64 * 8) {
-    int u[8];
+  for (int kb = rowptr[j] + lane; kb < je; kb += 64 * kWcBatch) {
+    int u[kWcBatch];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) u[q] = kb + 64 * q < je ? col[kb + 64 * q] : -1;
-    T y[8];
+    for (int q = 0; q < kWcBatch; ++q) u[q] = kb + 64 * q < je ? col[kb + 64 * q] : -1;
+    T y[kWcBatch];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) y[q] = u[q] >= 0 ? Y[static_cast<size_t>(u[q]) * B + c] : T(0);
+    for (int q = 0; q < kWcBatch; ++q) y[q] = u[q] >= 0 ? Y[static_cast<size_t>(u[q]) * B + c] : T(0);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < kWcBatch; ++q) {
       if (u[q] >= 0) {
         jmx = fmax(jmx, static_cast<double>(y[q]));
         jmn = fmin(jmn, static_cast<double>(y[q]));
