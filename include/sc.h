@@ -24,7 +24,12 @@
  *     arrays are host memory unless SC_DEVICE_PTRS is set in the options'
  *     flags, in which case they are device memory on the handle's device
  *     and results are stream-ordered on the options' stream;
- *   - with host outputs every call returns after the results are written.
+ *   - with host outputs every call returns after the results are written;
+ *   - sc_all_edges_ex runs the per-block tails (candidate summary, walk
+ *     counts, walks, the last step's accumulation) on a second stream owned
+ *     by the handle; it waits for the options' stream before its first
+ *     launch and the options' stream waits for it before the combine, so
+ *     the call stays ordered on the options' stream.
  */
 #ifndef SC_H
 #define SC_H
