@@ -202,9 +202,11 @@ int sc_all_edges(sc_graph* g, double eps, int L, double* out);
  * Random walks follow the Philox4x32-10 counter scheme documented in the
  * implementation (counter = (i, j, r, side*2^31 + step/4), key = seed).
  * Environment (read by the library, all optional): SC_COST_GATHER_BW,
- * SC_COST_STEP_FIXED, SC_COST_TAIL_FIXED, SC_COST_WALK_STEP and
- * SC_COST_OVERLAP override the constants of the switch-step cost model
- * (bytes/s, s, s, s per walk step, share); SC_WALK_CHUNK_CAPACITY caps the
+ * SC_COST_STEP_FIXED, SC_COST_SKIP_FRAC, SC_COST_TAIL_FIXED,
+ * SC_COST_TAIL_PER_NODE, SC_COST_WALK_STEP and SC_COST_OVERLAP override the
+ * constants of the switch-step cost model (bytes/s, s, fraction of a dense
+ * step, s, s per node, s per walk step, share);
+ * SC_WALK_CHUNK_CAPACITY caps the
  * walk chunk-sum buffer when it is first allocated (blocks whose walks do not
  * fit then walk one slot per wave; used by the tests).
  */

@@ -913,16 +913,21 @@ struct CostModel {
   double gather_bw;     // bytes/s of neighbour-row gathers in a dense step
   double step_fixed;    // s of fixed cost per dense step
   double twohop_frac;   // two-hop step cost relative to a dense step
-  double tail_fixed;    // s of the candidate summary and walk counts per block
+  double skip_frac;     // first dense step (zero rows skipped, B = 64) relative to a dense step
+  double tail_fixed;    // s of a block's tail launches besides the walks (their
+                        // chain of small launches under the traversal's load) ...
+  double tail_per_node; // ... plus this many s per node (passes over the block state)
   double walk_step;     // s per single-walk step
   double overlap;       // share of the shorter stream that still costs time
 };
 
 CostModel cost_model() {
-  CostModel c{7.5e12, 3.0e-6, 0.5, 6.0e-5, 3.5e-11, 0.25};
+  CostModel c{7.5e12, 3.0e-6, 0.3, 0.6, 5.5e-5, 3.5e-10, 3.5e-11, 0.25};
   if (const char* s = std::getenv("SC_COST_GATHER_BW")) c.gather_bw = std::atof(s);
   if (const char* s = std::getenv("SC_COST_STEP_FIXED")) c.step_fixed = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_SKIP_FRAC")) c.skip_frac = std::atof(s);
   if (const char* s = std::getenv("SC_COST_TAIL_FIXED")) c.tail_fixed = std::atof(s);
+  if (const char* s = std::getenv("SC_COST_TAIL_PER_NODE")) c.tail_per_node = std::atof(s);
   if (const char* s = std::getenv("SC_COST_WALK_STEP")) c.walk_step = std::atof(s);
   if (const char* s = std::getenv("SC_COST_OVERLAP")) c.overlap = std::atof(s);
   return c;
@@ -1024,6 +1029,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       // sample blocks: walk steps at every candidate switch point
       const CostModel cm = cost_model();
       const double dense = cm.step_fixed + static_cast<double>(g->d.nslots) * B * sizeof(T) / cm.gather_bw;
+      const double tail0 = cm.tail_fixed + cm.tail_per_node * static_cast<double>(n);
       const int nsamp = std::min(nblocks, 4);
       std::vector<double> cost(Lmax + 1, 0.0);
       for (int si = 0; si < nsamp; ++si) {
@@ -1053,11 +1059,16 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
         }
         for (int ell = 2; ell <= Lmax; ++ell) {
           const int steps = std::min(ell, tmax);
-          const double trav = steps >= 2 ? cm.step_fixed + dense * (cm.twohop_frac + (steps - 2)) : 0.0;
+          const double first = B == 64 ? cm.skip_frac : 1.0;   // l = 3
+          const double trav =
+              steps >= 2 ? cm.step_fixed +
+                               dense * (cm.twohop_frac + (steps >= 3 ? first + (steps - 3) : 0.0))
+                         : 0.0;
           // switch points beyond the 64 counter slots are not candidates
-          const double tail = ell < tmax ? (ell < 64 ? cm.tail_fixed + static_cast<double>(wk[2 * ell + 1]) * cm.walk_step
-                                                     : 1e30)
-                                         : cm.step_fixed;
+          const double tail =
+              ell < tmax ? (ell < 64 ? tail0 + static_cast<double>(wk[2 * ell + 1]) * cm.walk_step
+                                     : 1e30)
+                         : cm.step_fixed;
           cost[ell] += std::max(trav, tail) + cm.overlap * std::min(trav, tail);
         }
       }
