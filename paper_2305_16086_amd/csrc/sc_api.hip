@@ -922,7 +922,7 @@ struct CostModel {
 };
 
 CostModel cost_model() {
-  CostModel c{7.5e12, 3.0e-6, 0.3, 0.6, 5.5e-5, 3.5e-10, 3.5e-11, 0.25};
+  CostModel c{7.5e12, 3.0e-6, 0.3, 0.6, 5.5e-5, 3.5e-10, 2.5e-11, 0.25};
   if (const char* s = std::getenv("SC_COST_GATHER_BW")) c.gather_bw = std::atof(s);
   if (const char* s = std::getenv("SC_COST_STEP_FIXED")) c.step_fixed = std::atof(s);
   if (const char* s = std::getenv("SC_COST_SKIP_FRAC")) c.skip_frac = std::atof(s);
