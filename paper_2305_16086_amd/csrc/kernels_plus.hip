@@ -84,19 +84,37 @@ __device__ inline void list_last(const double (&lv)[kMaxGamma], const int (&li)[
 //     (Algorithm 3 lines 3-5, safe reading), extremes over N(s).
 // Chunk p of column c: pmx/pmn[c*kColParts + p], lists pv/pi[(p*B + c)*gamma + r].
 
+// Slot kbeg + i of a finished block: add its chunk sums in chunk order, divided
+// by n_r (nothing when the block walked one slot per wave: ctl[1] == 0).
+__device__ inline void walk_finish_slot(const FinishJob& f, int i) {
+  if (f.ctl[1] == 0 || i >= f.kend - f.kbeg) return;
+  const long long n_r = f.nr[f.kbeg + i];
+  if (n_r <= 0) return;
+  double acc = 0.0;
+  for (long long c = f.chunk_off[i]; c < f.chunk_off[i + 1]; ++c) acc += f.part[c];
+  f.gacc[f.kbeg + i] += acc / static_cast<double>(n_r);
+}
+
 // Workgroups after col_blocks carry the accumulation of the step held in Y
-// (acc; Algorithm 2 lines 10-11), saving a launch.
+// (acc; Algorithm 2 lines 10-11) and then a previous block's walk finish (fin),
+// saving launches.
 template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void k_colmax(int n, int rows_per_part, int nparts,
                                                      const T* __restrict__ Y,
                                                      T* __restrict__ pmx, T* __restrict__ pmn,
-                                                     int col_blocks, AccJob acc,
+                                                     int col_blocks, AccJob acc, int acc_blocks,
+                                                     FinishJob fin,
                                                      const int32_t* __restrict__ slot_row,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ inv_deg_d) {
   if (static_cast<int>(blockIdx.x) >= col_blocks) {
-    const int k = acc.kbeg + (blockIdx.x - col_blocks) * kThreads + threadIdx.x;
-    accumulate_half<T, B>(acc, slot_row, col, inv_deg_d, Y, k);
+    const int t = static_cast<int>(blockIdx.x) - col_blocks;
+    if (t < acc_blocks) {
+      const int k = acc.kbeg + t * kThreads + threadIdx.x;
+      accumulate_half<T, B>(acc, slot_row, col, inv_deg_d, Y, k);
+    } else {
+      walk_finish_slot(fin, (t - acc_blocks) * kThreads + static_cast<int>(threadIdx.x));
+    }
     return;
   }
   constexpr int G = 64 / B;
@@ -757,18 +775,8 @@ __global__ __launch_bounds__(kThreads) void k_walks_flat(
   }
 }
 
-__global__ void k_walk_finish(int kbeg, int kend, const long long* __restrict__ nr,
-                              const long long* __restrict__ chunk_off,
-                              const long long* __restrict__ ctl, const double* __restrict__ part,
-                              double* __restrict__ gacc) {
-  if (ctl[1] == 0) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kend - kbeg) return;
-  const long long n_r = nr[kbeg + i];
-  if (n_r <= 0) return;
-  double acc = 0.0;
-  for (long long c = chunk_off[i]; c < chunk_off[i + 1]; ++c) acc += part[c];
-  gacc[kbeg + i] += acc / static_cast<double>(n_r);
+__global__ void k_walk_finish(FinishJob f) {
+  walk_finish_slot(f, static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 }  // namespace
@@ -783,10 +791,11 @@ __global__ void k_walk_finish(int kbeg, int kend, const long long* __restrict__ 
 
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
-                           ColStats* cs, void* scratch, hipStream_t st, const AccJob* acc) {
+                           ColStats* cs, void* scratch, hipStream_t st, const AccJob* acc,
+                           const FinishJob* fin) {
   int ncols = B;
   if (s0 + ncols > g.n) ncols = g.n - s0;
-  if (ncols <= 0) return hipSuccess;
+  if (ncols <= 0) return fin ? launch_walk_finish(*fin, st) : hipSuccess;
   if (gamma > kMaxGamma || gamma < 0) return hipErrorInvalidValue;
   const int G = 64 / B;
   const int nparts = kColParts;
@@ -806,9 +815,12 @@ hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const
   const AccJob job = acc ? *acc : AccJob{};
   const int acc_blocks =
       job.gacc && job.kend > job.kbeg ? static_cast<int>(grid_for(job.kend - job.kbeg, kThreads)) : 0;
-  SC_DISPATCH_B(B, (k_colmax<T, kB><<<col_blocks + acc_blocks, kThreads, 0, st>>>(
-                        g.n, rows, nparts, Y, pmx, pmn, col_blocks, job, g.slot_row, g.col,
-                        g.inv_deg_d)));
+  const FinishJob fj = fin ? *fin : FinishJob{};
+  const int fin_blocks =
+      fj.gacc && fj.kend > fj.kbeg ? static_cast<int>(grid_for(fj.kend - fj.kbeg, kThreads)) : 0;
+  SC_DISPATCH_B(B, (k_colmax<T, kB><<<col_blocks + acc_blocks + fin_blocks, kThreads, 0, st>>>(
+                        g.n, rows, nparts, Y, pmx, pmn, col_blocks, job, acc_blocks, fj,
+                        g.slot_row, g.col, g.inv_deg_d)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   SC_DISPATCH_B(B, (k_colthresh<T, kB><<<ncols, 64 * kThreshWaves, 0, st>>>(
@@ -855,7 +867,8 @@ template <typename T>
 hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                         uint64_t seed, const T* Y, const int32_t* tau_slot,
                         const int64_t* nr_slot, double* gacc, const WalkScratch& ws,
-                        hipStream_t st) {
+                        hipStream_t st, FinishJob* defer) {
+  if (defer) *defer = FinishJob{};
   if (kend <= kbeg) return hipSuccess;
   const unsigned k0 = static_cast<unsigned>(seed & 0xFFFFFFFFull);
   const unsigned k1 = static_cast<unsigned>(seed >> 32);
@@ -871,15 +884,33 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
                         Y, tau_slot, nr, off, ctl, ws.part, gacc)));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_walk_finish<<<grid_for(kend - kbeg, 256), 256, 0, st>>>(kbeg, kend, nr, off, ctl, ws.part,
-                                                           gacc);
+  FinishJob f;
+  f.kbeg = kbeg;
+  f.kend = kend;
+  f.nr = nr_slot;
+  f.chunk_off = ws.chunk_off;
+  f.ctl = ws.ctl;
+  f.part = ws.part;
+  f.gacc = gacc;
+  if (defer) {
+    *defer = f;
+    return hipSuccess;
+  }
+  return launch_walk_finish(f, st);
+}
+
+hipError_t launch_walk_finish(const FinishJob& f, hipStream_t st) {
+  if (!f.gacc || f.kend <= f.kbeg) return hipSuccess;
+  k_walk_finish<<<grid_for(f.kend - f.kbeg, 256), 256, 0, st>>>(f);
   return hipGetLastError();
 }
 
 template hipError_t launch_colstats<float>(const DeviceGraph&, int, int, int, const float*,
-                                           ColStats*, void*, hipStream_t, const AccJob*);
+                                           ColStats*, void*, hipStream_t, const AccJob*,
+                                           const FinishJob*);
 template hipError_t launch_colstats<double>(const DeviceGraph&, int, int, int, const double*,
-                                            ColStats*, void*, hipStream_t, const AccJob*);
+                                            ColStats*, void*, hipStream_t, const AccJob*,
+                                            const FinishJob*);
 template hipError_t launch_walk_counts<float>(const DeviceGraph&, int, int, int, int, int, int,
                                               double, int64_t, const float*, const ColStats*,
                                               const int32_t*, int64_t*, hipStream_t);
@@ -888,9 +919,9 @@ template hipError_t launch_walk_counts<double>(const DeviceGraph&, int, int, int
                                                const int32_t*, int64_t*, hipStream_t);
 template hipError_t launch_walks<float>(const DeviceGraph&, int, int, int, int, int, uint64_t,
                                         const float*, const int32_t*, const int64_t*, double*,
-                                        const WalkScratch&, hipStream_t);
+                                        const WalkScratch&, hipStream_t, FinishJob*);
 template hipError_t launch_walks<double>(const DeviceGraph&, int, int, int, int, int, uint64_t,
                                          const double*, const int32_t*, const int64_t*, double*,
-                                         const WalkScratch&, hipStream_t);
+                                         const WalkScratch&, hipStream_t, FinishJob*);
 
 }  // namespace sc

@@ -1103,6 +1103,9 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   const auto host0 = std::chrono::steady_clock::now();
   constexpr int D = sc::kPipeDepth;
   bool tail_recorded[D] = {};
+  // the last pass of a block's walks rides on the next candidate summary's
+  // first launch (same stream, before the next walks reuse the chunk buffers)
+  sc::FinishJob fin;
   for (int b = 0; b < nblocks; ++b) {
     int s0, kbeg, kend, tmax;
     block_range(b, &s0, &kbeg, &kend, &tmax);
@@ -1132,12 +1135,13 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
         if (rc) return rc;
       }
       HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, sb,
-                                     fuse_acc ? &R.pending_acc : nullptr));
+                                     fuse_acc ? &R.pending_acc : nullptr, &fin));
       R.pending_acc = sc::AccJob{};
+      fin = sc::FinishJob{};
       HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
                                         R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, sb));
       HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
-                                  g->tau_slot, g->nr_slot, g->gacc, g->walk, sb));
+                                  g->tau_slot, g->nr_slot, g->gacc, g->walk, sb, &fin));
     }
     HIP_TRY(hipEventRecord(g->pipe_ev[1 + D + pair], sb));
     tail_recorded[pair] = true;
@@ -1145,6 +1149,7 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   }
   R.stats.host_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
+  HIP_TRY(sc::launch_walk_finish(fin, sb));
   HIP_TRY(hipEventRecord(g->pipe_ev[0], sb));
   HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[0], 0));
   R.po = 0;

@@ -194,6 +194,18 @@ template <typename T>
 hipError_t launch_accumulate(const DeviceGraph& g, int B, const T* Y, const AccJob& acc,
                              hipStream_t st);
 
+// Last pass of a block's flattened walks: gacc[k] += (slot k's chunk sums in
+// chunk order) / n_r.  It may ride on a later launch of the same stream that
+// comes before the next block's walks (which reuse chunk_off, part and ctl).
+struct FinishJob {
+  int kbeg = 0, kend = 0;
+  const int64_t* nr = nullptr;
+  const int64_t* chunk_off = nullptr;
+  const int64_t* ctl = nullptr;
+  const double* part = nullptr;
+  double* gacc = nullptr;   // null: no job
+};
+
 // Algorithm 3 summary per column of the block (top-gamma, rho bound, extremes).
 // scratch: kColScratchBytes of device memory.
 constexpr int kColParts = 2048;  // row chunks of the coalesced first pass (multiple of 4 * 64/B)
@@ -201,10 +213,12 @@ constexpr size_t kColScratchBytes =
     static_cast<size_t>(kColParts) * 64 *
         (kMaxGamma * (sizeof(double) + sizeof(int)) + 2 * sizeof(double) + sizeof(int)) +
     64 * (sizeof(int) + sizeof(double));
+// acc / fin (optional): an accumulation step and a previous block's walk
+// finish carried by the first launch as extra workgroups.
 template <typename T>
 hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const T* Y,
                            ColStats* cs, void* scratch, hipStream_t st,
-                           const AccJob* acc = nullptr);
+                           const AccJob* acc = nullptr, const FinishJob* fin = nullptr);
 
 // n_r per slot (Eq. 13 with chi of Eq. 17 / Eq. 15); 0 where tau_k <= tilde.
 template <typename T>
@@ -217,7 +231,7 @@ hipError_t launch_walk_counts(const DeviceGraph& g, int kbeg, int kend, int s0, 
 hipError_t launch_work_totals(int kbeg, int kend, int tilde, const int32_t* tau_slot,
                               const int64_t* nr_slot, unsigned long long* work, hipStream_t st);
 
-// Scratch of the flattened walks (all null: one wave per half-edge instead).
+// Scratch of the flattened walks (required by launch_walks).
 struct WalkScratch {
   int64_t* chunk_off = nullptr;   // [slots of a block + 1]
   double* part = nullptr;         // [capacity] chunk sums
@@ -225,13 +239,18 @@ struct WalkScratch {
   int64_t* ctl = nullptr;         // [2]
 };
 
+
 // Walk tail: gacc[k] += mean_r X_r (Eq. 11) for the block's slots (ws must hold
 // the chunk buffers; blocks whose chunks do not fit walk one slot per wave).
+// With defer, the last pass is not launched but returned in *defer (gacc null
+// when there is none); the caller runs it with launch_walk_finish or carries
+// it on launch_colstats.
 template <typename T>
 hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int tilde,
                         uint64_t seed, const T* Y, const int32_t* tau_slot,
                         const int64_t* nr_slot, double* gacc, const WalkScratch& ws,
-                        hipStream_t st);
+                        hipStream_t st, FinishJob* defer = nullptr);
+hipError_t launch_walk_finish(const FinishJob& job, hipStream_t st);
 
 // out[e] = gacc[slot(u_e->v_e)] + gacc[slot(v_e->u_e)] (Algorithm 2 line 12).
 hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,
