@@ -13,7 +13,16 @@ __device__ inline void accumulate_half(const AccJob& acc, const int32_t* __restr
                                        const int32_t* __restrict__ col,
                                        const double* __restrict__ inv_deg_d,
                                        const T* __restrict__ Y, int k) {
-  if (k >= acc.kend || acc.ell > acc.tau[k]) return;
+  if (k >= acc.kend) return;
+  if (acc.rdiag) {   // recording job
+    const int s = slot_row[k];
+    const int c = s - acc.s0;
+    const int64_t o = static_cast<int64_t>(k) * (kRecSteps + 1) + acc.ell;
+    static_cast<T*>(acc.rdiag)[o] = Y[static_cast<size_t>(s) * B + c];
+    static_cast<T*>(acc.roff)[o] = Y[static_cast<size_t>(col[k]) * B + c];
+    return;
+  }
+  if (acc.ell > acc.tau[k]) return;
   const int s = slot_row[k];
   const int c = s - acc.s0;
   const int j = col[k];

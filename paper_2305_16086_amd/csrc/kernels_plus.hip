@@ -814,7 +814,7 @@ hipError_t launch_colstats(const DeviceGraph& g, int s0, int B, int gamma, const
   const int col_blocks = waves / kWavesPerBlock;
   const AccJob job = acc ? *acc : AccJob{};
   const int acc_blocks =
-      job.gacc && job.kend > job.kbeg ? static_cast<int>(grid_for(job.kend - job.kbeg, kThreads)) : 0;
+      acc_job_set(job) ? static_cast<int>(grid_for(job.kend - job.kbeg, kThreads)) : 0;
   const FinishJob fj = fin ? *fin : FinishJob{};
   const int fin_blocks =
       fj.gacc && fj.kend > fj.kbeg ? static_cast<int>(grid_for(fj.kend - fj.kbeg, kThreads)) : 0;

@@ -779,7 +779,7 @@ RowArgs<T> row_args(const DeviceGraph& g, int B, T* partials, const AccJob& acc)
 }
 
 inline int acc_blocks(const AccJob& acc) {
-  return acc.gacc && acc.kend > acc.kbeg ? static_cast<int>(grid_for(acc.kend - acc.kbeg, kThreads))
+  return acc_job_set(acc) ? static_cast<int>(grid_for(acc.kend - acc.kbeg, kThreads))
                                           : 0;
 }
 

@@ -217,15 +217,18 @@ struct Runner {
 
   AccJob pending_acc;     // accumulation of the latest step, not yet launched
 
-  int record_step(int s0, int kbeg, int kend, int ell) {
-    if (rdiag && ell <= record_to)
+  // recordings of step ell next to an accumulation (without one, the
+  // recording is the pending job itself and rides on the next launch)
+  int record_step(int s0, int kbeg, int kend, int ell, bool acc) {
+    if (acc && rdiag && ell <= record_to)
       HIP_TRY(launch_record<T>(g->d, kbeg, kend, s0, B, ell, Yb(cur), rdiag, roff, st));
     return SC_OK;
   }
 
   // launches the pending accumulation on its own
   int flush_acc() {
-    if (pending_acc.gacc) HIP_TRY(launch_accumulate<T>(g->d, B, Yb(cur), pending_acc, st));
+    if (acc_job_set(pending_acc))
+      HIP_TRY(launch_accumulate<T>(g->d, B, Yb(cur), pending_acc, st));
     pending_acc = AccJob{};
     return SC_OK;
   }
@@ -275,11 +278,18 @@ struct Runner {
         j.ell = ell;
         j.tau = g->tau_slot;
         j.gacc = gacc;
+      } else if (rdiag && ell <= record_to) {
+        j.kbeg = kbeg;
+        j.kend = kend;
+        j.s0 = s0;
+        j.ell = ell;
+        j.rdiag = rdiag;
+        j.roff = roff;
       }
       return j;
     };
     pending_acc = job(2);
-    int rc = record_step(s0, kbeg, kend, 2);
+    int rc = record_step(s0, kbeg, kend, 2, acc);
     if (rc) return rc;
     for (int ell = 3; ell <= lend; ++ell) {
       hipEvent_t a = nullptr, b = nullptr;
@@ -311,7 +321,7 @@ struct Runner {
       }
       cur = 1 - cur;
       pending_acc = job(ell);
-      rc = record_step(s0, kbeg, kend, ell);
+      rc = record_step(s0, kbeg, kend, ell, acc);
       if (rc) return rc;
     }
     return SC_OK;

@@ -44,12 +44,17 @@ struct ColStats {
 };
 
 // Per-edge accumulation job of one source block: slots [kbeg, kend) of the
-// block starting at s0 gain the step-ell term (gacc == nullptr: no job).
+// block starting at s0 gain the step-ell term (gacc == nullptr: no job).  With
+// rdiag set instead, the job records p_ell(s,s) and p_ell(j,s) of every slot
+// into rdiag / roff (T[slots][L0 + 1], the learned closure's recordings).
 struct AccJob {
   int kbeg = 0, kend = 0, s0 = 0, ell = 0;
   const int32_t* tau = nullptr;
   double* gacc = nullptr;
+  void* rdiag = nullptr;
+  void* roff = nullptr;
 };
+inline bool acc_job_set(const AccJob& a) { return (a.gacc || a.rdiag) && a.kend > a.kbeg; }
 
 // Neighbour-bit update of the two-hop masks: set the bits of block s_set in
 // buffer buf, clear those of block s_clear in buffer 1 - buf (s_* < 0: none).

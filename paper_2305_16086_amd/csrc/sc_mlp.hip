@@ -290,8 +290,10 @@ int record_and_features(sc_graph* g, int B, hipStream_t st, double lam, float* X
     int s0b, kbeg, kend, tmax;
     R.block_range(b, dummy_tau, &s0b, &kbeg, &kend, &tmax);
     // the next block's neighbour masks ride on this block's first dense step
-    const int rc = R.traverse(s0b, kbeg, kend, sc::kRecSteps, false, nullptr,
-                              b + 1 < nblocks ? s0b + B : -1);
+    int rc = R.traverse(s0b, kbeg, kend, sc::kRecSteps, false, nullptr,
+                        b + 1 < nblocks ? s0b + B : -1);
+    if (rc) return rc;
+    rc = R.flush_acc();   // the last step's recording
     if (rc) return rc;
   }
   {
