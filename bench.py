@@ -32,8 +32,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
 # HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
 # scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
 # kernel source they were taken on (first 16 hex digits of its SHA-256)
-PROP_TRAFFIC_BYTES = 419353687
-PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "1f56775a1ff74c3b")
+PROP_TRAFFIC_BYTES = 419492460
+PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "5e8964662d067ee8")
 
 
 def measured_traffic():
