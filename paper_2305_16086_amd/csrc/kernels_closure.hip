@@ -64,6 +64,53 @@ __global__ void k_record(int kbeg, int kend, int s0, int ell, const int32_t* __r
   roff[static_cast<int64_t>(k) * kRec + ell] = Y[static_cast<size_t>(col[k]) * B + c];
 }
 
+// The last recorded step without a full dense step: only p_L(s,s) and p_L(j,s)
+// of the block's slots are read, so each is summed from the neighbour rows of
+// Y = the state at L - 1 directly (Algorithm 2 lines 6-9 restricted to those
+// rows).  Waves [0, nsrc) take a source s = s0 + w (p_L(s,s) for all its
+// slots), the others one slot k = (s -> j) each (p_L(j,s), and the step L - 1
+// recordings read from Y).  Lanes stride over the neighbours; fixed butterfly.
+template <typename T>
+__device__ inline T wave_sum_t(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_record_last(
+    int kbeg, int kend, int s0, int nsrc, int ell, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const int32_t* __restrict__ slot_row,
+    const T* __restrict__ inv_deg, const T* __restrict__ Y, T* __restrict__ rdiag,
+    T* __restrict__ roff) {
+  const int lane = threadIdx.x & 63;
+  const int w = static_cast<int>(blockIdx.x) * kWavesPerBlock + static_cast<int>(threadIdx.x >> 6);
+  if (w < nsrc) {
+    const int s = s0 + w;
+    const int b = rowptr[s], e = rowptr[s + 1];
+    T sum = T(0);
+    for (int q = b + lane; q < e; q += 64) sum += Y[static_cast<size_t>(col[q]) * B + w];
+    const T p = wave_sum_t(sum) * inv_deg[s];
+    for (int q = b + lane; q < e; q += 64) rdiag[static_cast<int64_t>(q) * kRec + ell] = p;
+    return;
+  }
+  const int k = kbeg + (w - nsrc);
+  if (k >= kend) return;
+  const int s = slot_row[k];
+  const int c = s - s0;
+  const int j = col[k];
+  const int b = rowptr[j], e = rowptr[j + 1];
+  T sum = T(0);
+  for (int q = b + lane; q < e; q += 64) sum += Y[static_cast<size_t>(col[q]) * B + c];
+  sum = wave_sum_t(sum);
+  if (lane == 0) {
+    const int64_t o = static_cast<int64_t>(k) * kRec;
+    roff[o + ell] = sum * inv_deg[j];
+    rdiag[o + ell - 1] = Y[static_cast<size_t>(s) * B + c];
+    roff[o + ell - 1] = Y[static_cast<size_t>(j) * B + c];
+  }
+}
+
 // ------------------------------------------------------------------ features and bounds
 __device__ inline double sdiv(double a, double b) { return b != 0.0 ? a / b : 0.0; }
 
@@ -547,6 +594,19 @@ hipError_t launch_record(const DeviceGraph& g, int kbeg, int kend, int s0, int B
 }
 
 template <typename T>
+hipError_t launch_record_last(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
+                              const T* Y, T* rdiag, T* roff, hipStream_t st) {
+  if (kend <= kbeg || ell < 3 || ell >= kRec) return hipErrorInvalidValue;
+  const int nsrc = static_cast<int>(std::min<int64_t>(B, static_cast<int64_t>(g.n) - s0));
+  if (nsrc <= 0) return hipErrorInvalidValue;
+  const int waves = nsrc + (kend - kbeg);
+  SC_DISPATCH_B(B, (k_record_last<T, kB><<<grid_for(waves, kWavesPerBlock), kThreads, 0, st>>>(
+                        kbeg, kend, s0, nsrc, ell, g.rowptr, g.col, g.slot_row, inv_deg_sel<T>(g),
+                        Y, rdiag, roff)));
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_features(const DeviceGraph& g, const T* rdiag, const T* roff, double lam,
                            float* X, double* s0, double* uK, double* lo, double* hi,
                            hipStream_t st) {
@@ -632,6 +692,10 @@ template hipError_t launch_record<float>(const DeviceGraph&, int, int, int, int,
                                          float*, float*, hipStream_t);
 template hipError_t launch_record<double>(const DeviceGraph&, int, int, int, int, int,
                                           const double*, double*, double*, hipStream_t);
+template hipError_t launch_record_last<float>(const DeviceGraph&, int, int, int, int, int,
+                                              const float*, float*, float*, hipStream_t);
+template hipError_t launch_record_last<double>(const DeviceGraph&, int, int, int, int, int,
+                                               const double*, double*, double*, hipStream_t);
 template hipError_t launch_features<float>(const DeviceGraph&, const float*, const float*, double,
                                            float*, double*, double*, double*, double*,
                                            hipStream_t);

@@ -275,6 +275,11 @@ hipError_t launch_record_init(const DeviceGraph& g, T* rdiag, T* roff, hipStream
 template <typename T>
 hipError_t launch_record(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
                          const T* Y, T* rdiag, T* roff, hipStream_t st);
+// Recordings of steps ell - 1 and ell of a block from the state at ell - 1
+// (no dense step for ell); 3 <= ell <= kRecSteps.
+template <typename T>
+hipError_t launch_record_last(const DeviceGraph& g, int kbeg, int kend, int s0, int B, int ell,
+                              const T* Y, T* rdiag, T* roff, hipStream_t st);
 template <typename T>
 hipError_t launch_features(const DeviceGraph& g, const T* rdiag, const T* roff, double lam,
                            float* X, double* s0, double* uK, double* lo, double* hi,

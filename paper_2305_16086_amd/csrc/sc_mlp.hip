@@ -290,11 +290,15 @@ int record_and_features(sc_graph* g, int B, hipStream_t st, double lam, float* X
     int s0b, kbeg, kend, tmax;
     R.block_range(b, dummy_tau, &s0b, &kbeg, &kend, &tmax);
     // the next block's neighbour masks ride on this block's first dense step
-    int rc = R.traverse(s0b, kbeg, kend, sc::kRecSteps, false, nullptr,
-                        b + 1 < nblocks ? s0b + B : -1);
+    // steps 2 .. L0 - 1 (recordings ride on the next launch), then steps
+    // L0 - 1 and L0 recorded from the state at L0 - 1 (no full last step)
+    const int rc = R.traverse(s0b, kbeg, kend, sc::kRecSteps - 1, false, nullptr,
+                              b + 1 < nblocks ? s0b + B : -1);
     if (rc) return rc;
-    rc = R.flush_acc();   // the last step's recording
-    if (rc) return rc;
+    R.pending_acc = sc::AccJob{};
+    if (kend > kbeg)
+      HIP_TRY(sc::launch_record_last<T>(g->d, kbeg, kend, s0b, B, sc::kRecSteps, R.Yb(R.cur),
+                                        R.rdiag, R.roff, st));
   }
   {
     const int rc = R.flush_masks();
