@@ -153,3 +153,12 @@ def test_learned_closure_end_to_end(env):
     plain, _ = sc.sc_all_edges_ex(g, eps, 0, sc.sc_default_options(method=sc.SC_TGT, precision=0))
     assert st2["fallback_edges"] == len(u)
     np.testing.assert_array_equal(out2, plain)
+    # narrower source blocks (other row-sum orders, the last recorded step with
+    # fewer columns): still certified, the same closure up to rounding
+    for blk in (32, 16):
+        o3 = sc.sc_default_options(method=sc.SC_LEARNED, precision=0, mlp=net.handle.value,
+                                   block=blk)
+        out3, st3 = sc.sc_all_edges_ex(g, eps, 0, o3)
+        assert np.abs(out3 - exact).max() <= eps
+        assert abs(st3["fallback_edges"] - st["fallback_edges"]) <= max(2, len(u) // 100)
+        assert np.median(np.abs(out3 - out)) <= 1e-6
