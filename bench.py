@@ -31,17 +31,23 @@ HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
 # HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
 # scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
-# kernel source they were taken on (first 16 hex digits of its SHA-256)
+# kernel sources they were taken on (first 16 hex digits of the SHA-256 of the files in order)
 PROP_TRAFFIC_BYTES = 419492460
-PROP_TRAFFIC_SOURCE = ("paper_2305_16086_amd/csrc/kernels_tgt.hip", "5e8964662d067ee8")
+PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
+                        "paper_2305_16086_amd/csrc/accumulate.hpp"), "b5f84bdd2dc37d24")
+
+
+def traffic_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PROP_TRAFFIC_SOURCE[0]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
-    import hashlib
-    path = os.path.join(ROOT, PROP_TRAFFIC_SOURCE[0])
-    with open(path, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()[:16]
-    return PROP_TRAFFIC_BYTES if digest == PROP_TRAFFIC_SOURCE[1] else None
+    return PROP_TRAFFIC_BYTES if traffic_source_digest() == PROP_TRAFFIC_SOURCE[1] else None
 
 
 def parse():
