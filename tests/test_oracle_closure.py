@@ -3,6 +3,9 @@
 * the certified interval of the tail (log-convexity of the pair sums of the
   Eq. 18 series) against exact tails from the Laplacian pseudoinverse;
 * feature symmetry under swapping the endpoints;
+* all sixteen features equal to their closed forms on distance-regular graphs
+  (K_n, odd C_n, Petersen), where the series terms follow from the spectrum
+  alone, and a planted swap of two features fails that check;
 * the network gradient against central finite differences, and the forward
   pass against a hand-built network with a closed-form output;
 * Adam against its first-step closed form (the update is lr * sign(g)).
@@ -93,3 +96,97 @@ def test_adam_first_step_is_signed_lr():
     new, m1, m2 = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
     np.testing.assert_allclose(new, -0.01 * np.sign(g), rtol=1e-12)
     assert mlp.NPARAM == 5313
+
+
+# ---------------------------------------------------------------- closed-form features
+#
+# On a distance-regular graph (K_n, odd C_n, Petersen) every node sees the same
+# spectrum: with the eigenvalues lambda_k of P and multiplicities mult_k,
+# p_l(i,i) = (1/n) sum_k mult_k lambda_k^l, and since all neighbours of i are
+# alike, p_l(j,i) = (1/d) sum_{x in N(i)} p_l(x,i) = p_{l+1}(i,i).  The series
+# terms are then t_l = (2/d)(p_l(i,i) - p_{l+1}(i,i)) on every edge, with no
+# traversal involved; the sixteen features follow from their definitions.
+
+def _drg_spectrum(name, n):
+    if name == "K":
+        return np.array([1.0, -1.0 / (n - 1)]), np.array([1, n - 1]), n - 1
+    if name == "C":
+        lam = np.cos(2 * np.pi * np.arange(n) / n)
+        return lam, np.ones(n), 2
+    assert name == "Petersen"
+    return np.array([1.0, 1.0 / 3.0, -2.0 / 3.0]), np.array([1, 5, 4]), 3
+
+
+def _closed_form_features(name, n, m):
+    lam, mult, d = _drg_spectrum(name, n)
+    pii = np.array([(mult * lam ** ell).sum() / n for ell in range(cl.L0 + 2)])
+    pji = pii[1:]
+    t = 2.0 / d * (pii[:-1] - pji)                          # t_0 .. t_8
+    u = np.array([t[2 * k] + t[2 * k + 1] for k in range(cl.K + 1)])
+    F = np.empty(cl.NFEAT)
+    F[0], F[1] = 2.0 / d, 1.0 / d ** 2
+    F[2:5] = u[1:4] / u[0:3]
+    F[5] = t[8] / u[3]
+    F[6:9] = m * 2.0 * pii[6:9] / d
+    F[9:12] = m * 2.0 * pji[6:9] / d
+    F[12:15] = t[1:4] / t[0]
+    F[15] = u[3] / t[0]
+    return F
+
+
+def _drg_graph(name, n):
+    if name == "K":
+        return gg.complete_graph(n)
+    if name == "C":
+        return gg.cycle_graph(n)
+    return gg.petersen_graph()
+
+
+DRG_CASES = [("K", 5), ("K", 8), ("C", 7), ("C", 11), ("Petersen", 10)]
+
+
+def check_features_closed_form(features_fn):
+    for name, n in DRG_CASES:
+        graph = _drg_graph(name, n)
+        G, diag, off = records(graph)
+        _, u, v = graph
+        F = features_fn(diag, off, G.deg, u, v)
+        expect = _closed_form_features(name, n, len(u))
+        # t_8 is a difference of two probabilities near 1/n that differ by
+        # |lambda|^8 (7^-8 on K_8): the ratios keep ~1e-16 / |lambda|^8 relative rounding
+        np.testing.assert_allclose(F, np.broadcast_to(expect, F.shape), rtol=1e-8, atol=1e-13,
+                                   err_msg=f"{name}{n}")
+
+
+def test_features_equal_closed_forms_on_distance_regular_graphs():
+    check_features_closed_form(cl.features)
+
+
+def test_complete_graph_features_by_hand():
+    # K_n: lambda = -1/(n-1) (multiplicity n-1), d = n-1, m = n(n-1)/2, and
+    # t_l = 2 lambda^l / d, so r_k = lambda^2, t_8/u_3 = lambda^2/(1+lambda),
+    # m a_l = 1 + d lambda^l, m b_l = 1 - lambda^l, t_l/t_0 = lambda^l,
+    # u_3/t_0 = lambda^6 (1 + lambda)
+    n = 6
+    lam, d = -1.0 / (n - 1), n - 1
+    graph = gg.complete_graph(n)
+    G, diag, off = records(graph)
+    F = cl.features(diag, off, G.deg, graph[1], graph[2])
+    expect = [2.0 / d, 1.0 / d ** 2, lam ** 2, lam ** 2, lam ** 2, lam ** 2 / (1 + lam),
+              1 + d * lam ** 6, 1 + d * lam ** 7, 1 + d * lam ** 8,
+              1 - lam ** 6, 1 - lam ** 7, 1 - lam ** 8,
+              lam, lam ** 2, lam ** 3, lam ** 6 * (1 + lam)]
+    np.testing.assert_allclose(F, np.broadcast_to(expect, F.shape), rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("swap", [(2, 3), (3, 4), (6, 9), (12, 13), (5, 15)])
+def test_planted_feature_swap_is_caught(swap):
+    a, b = swap
+
+    def swapped(*args, **kw):
+        F = cl.features(*args, **kw)
+        F[:, [a, b]] = F[:, [b, a]]
+        return F
+
+    with pytest.raises(AssertionError):
+        check_features_closed_form(swapped)
