@@ -116,6 +116,18 @@ typedef struct sc_stats {
                               kernel's own start and end)                          */
   double host_ms;          /* host time spent issuing the block loop (the GPU work
                               queued behind it runs meanwhile)                     */
+  int64_t L_capped;        /* edges whose automatic truncation was cut to max_L: the
+                              error bound of Theorem 3.2 does not cover them (always 0
+                              with a fixed L)                                        */
+  int32_t lambda_converged;/* 1: lambda* from Lanczos runs whose extreme Ritz pairs
+                              passed the residual test; 0: a run reached its step limit
+                              first (the value is then an estimate only); -1: lambda*
+                              given by the caller or not needed                      */
+  int32_t tilde_min;       /* smallest per-source switch step (TGT+), else -1         */
+  int32_t tilde_max;       /* largest per-source switch step (TGT+), else -1          */
+  int32_t reserved_;
+  int64_t push_edges;      /* SC_PER_SOURCE: neighbour-list entries pushed by the
+                              frontier-sparse traversal, else 0                     */
 } sc_stats;
 
 /* Fill *o with defaults: TGT, FP32, gamma 10, delta 1/n, seed 0x5C5C, auto tilde_tau. */
@@ -248,6 +260,17 @@ void sc_mlp_free(sc_mlp* net);
 int sc_mlp_get(const sc_mlp* net, float* params, float* norm, float* range);
 int sc_mlp_set(sc_mlp* net, const float* params, const float* norm, const float* range);
 
+/* Write the network (parameters, normalisation and feature range) to a file
+ * (binary, little-endian, with a checksum; the layout is documented in the
+ * implementation).  Adam's moments are not saved.  Errors: SC_EINVAL when the
+ * file cannot be written.  The network is unchanged. */
+int sc_mlp_save(const sc_mlp* net, const char* path);
+
+/* New network from a file written by sc_mlp_save on the current device;
+ * *out is NULL on error (SC_EINVAL: missing file, wrong size, header or
+ * checksum, NaN values). */
+int sc_mlp_load(const char* path, sc_mlp** out);
+
 /* Training data of one graph: features X [m][16] (from the first 8 steps),
  * targets z = (s_Lref - s_7)/u3 and weights w (0 where u3 = 0), with s_Lref
  * from TGT at the uniform odd truncation L_ref (e.g. 201).  Device pointers. */
@@ -309,7 +332,10 @@ void sc_free_batch(sc_batch* b);
  * All-edge SC of every graph.  L: NULL (all automatic) or G ints, L[g] as
  * the L argument of sc_all_edges (0 automatic, > 0 fixed odd-rounded).
  * o: method must be SC_TGT; precision, max_L, lambda_star (applied to every
- * graph when > 0), stream and flags as for sc_all_edges_ex; block: 0 = the
+ * graph when > 0), stream and flags as for sc_all_edges_ex; with
+ * SC_TAU_SPECTRAL every automatic graph that holds a spectrum
+ * (sc_compute_spectrum / sc_set_spectrum on sc_batch_graph) takes CalTau
+ * (Algorithm 1), the others the lambda*-bound; block: 0 = the
  * tuned width of the graph's size bucket (sc_batch_autotune /
  * sc_batch_load_tuning), else a built-in choice; or 1, 2, 4, 8, 16, 32, 64
  * for every graph.  SC_GRAPH_REPLAY records the device work (truncation,
@@ -318,8 +344,10 @@ void sc_free_batch(sc_batch* b);
  * while the arguments (and output pointers) stay the same.
  * out: G pointers; out[g] receives m[g] doubles in graph g's input edge
  * order (host memory, or device memory with SC_DEVICE_PTRS).
- * st (may be NULL): L_used / L_min over all graphs, block (-1 when mixed),
- * largest lambda*, prop_launches = persistent launches, prop_ms = their time
+ * st (may be NULL): L_used / L_min over all graphs, L_capped (edges of all
+ * graphs whose automatic length was cut to max_L), block (-1 when mixed),
+ * largest lambda* (|lambda_2| of the spectrum for CalTau graphs),
+ * prop_launches = persistent launches, prop_ms = their time
  * (SC_TIME_KERNELS, not with SC_GRAPH_REPLAY), total_ms.
  */
 int sc_batch_all_edges(sc_batch* b, double eps, const int32_t* L, const sc_options* o,

@@ -423,9 +423,10 @@ __device__ inline int graph_of(const int64_t* __restrict__ off, int G, int64_t i
 
 __global__ void k_batch_prologue(const BatchGraph* __restrict__ graphs,
                                  const int64_t* __restrict__ node_off, int G, int64_t total,
-                                 int32_t* mm) {
+                                 int32_t* mm, unsigned long long* capped) {
   const int64_t X = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   int tlo = INT_MAX, thi = 0;
+  int ncap = 0;
   if (X < total) {
     const int gi = graph_of(node_off, G, X);
     const BatchGraph& g = graphs[gi];
@@ -436,8 +437,17 @@ __global__ void k_batch_prologue(const BatchGraph* __restrict__ graphs,
       int tmax = 0;
       for (int k = g.rowptr[x]; k < g.rowptr[x + 1]; ++k) {
         const int j = g.col[k];
-        const int t = tau_of(g.L, di, static_cast<double>(g.deg[j]), eps_tau, g.lam, g.max_L);
-        const_cast<int32_t*>(g.tau_slot)[k] = t;
+        int t;
+        if (g.L < 0) {
+          t = g.tau_slot[k];   // CalTau wrote it (and counted its own capped slots)
+        } else {
+          t = tau_uncapped(g.L, di, static_cast<double>(g.deg[j]), eps_tau, g.lam);
+          if (g.L == 0 && t > g.max_L) {
+            t = g.max_L;
+            ++ncap;
+          }
+          const_cast<int32_t*>(g.tau_slot)[k] = t;
+        }
         tmax = t > tmax ? t : tmax;
         double v = g.inv_d[x];                       // l = 0: p_0(x,x)/d_x
         if (t >= 1) v -= g.inv_d[j] * g.inv_d[x];    // l = 1: -p_1(j,x)/d_x
@@ -453,10 +463,12 @@ __global__ void k_batch_prologue(const BatchGraph* __restrict__ graphs,
     for (int off = 32; off >= 1; off >>= 1) {
       tlo = min(tlo, __shfl_xor(tlo, off, 64));
       thi = max(thi, __shfl_xor(thi, off, 64));
+      ncap += __shfl_xor(ncap, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
       if (tlo != INT_MAX) atomicMin(&mm[0], tlo);
       atomicMax(&mm[1], thi);
+      if (capped && ncap > 0) atomicAdd(capped, static_cast<unsigned long long>(ncap));
     }
   }
 }
@@ -550,10 +562,11 @@ hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st) {
 }
 
 hipError_t launch_batch_prologue(const BatchGraph* graphs, const int64_t* node_off, int G,
-                                 int64_t total_rows, int32_t* mm, hipStream_t st) {
+                                 int64_t total_rows, int32_t* mm, unsigned long long* capped,
+                                 hipStream_t st) {
   if (total_rows <= 0) return hipSuccess;
   k_batch_prologue<<<static_cast<unsigned>((total_rows + 255) / 256), 256, 0, st>>>(
-      graphs, node_off, G, total_rows, mm);
+      graphs, node_off, G, total_rows, mm, capped);
   return hipGetLastError();
 }
 

@@ -49,15 +49,21 @@ __global__ __launch_bounds__(kThreads) void k_tau(int n, const int32_t* __restri
                                                   const int32_t* __restrict__ deg, int L,
                                                   double eps_tau, double lam, int max_L,
                                                   int32_t* __restrict__ tau_slot,
-                                                  int32_t* __restrict__ tau_row) {
+                                                  int32_t* __restrict__ tau_row,
+                                                  unsigned long long* __restrict__ capped) {
   const int x = blockIdx.x * kWavesPerBlock + static_cast<int>(threadIdx.x) / 64;
   const int lane = static_cast<int>(threadIdx.x) & 63;
   if (x >= n) return;   // uniform per wave
   int tmax = 0;
+  int ncap = 0;
   const double di = static_cast<double>(deg[x]);
   const int end = rowptr[x + 1];
   for (int k = rowptr[x] + lane; k < end; k += 64) {
-    const int t = tau_of(L, di, static_cast<double>(deg[col[k]]), eps_tau, lam, max_L);
+    int t = tau_uncapped(L, di, static_cast<double>(deg[col[k]]), eps_tau, lam);
+    if (L <= 0 && t > max_L) {
+      t = max_L;
+      ++ncap;
+    }
     tau_slot[k] = t;
     tmax = t > tmax ? t : tmax;
   }
@@ -65,8 +71,12 @@ __global__ __launch_bounds__(kThreads) void k_tau(int n, const int32_t* __restri
   for (int off = 32; off >= 1; off >>= 1) {
     const int o = __shfl_xor(tmax, off, 64);
     tmax = o > tmax ? o : tmax;
+    ncap += __shfl_xor(ncap, off, 64);
   }
-  if (lane == 0) tau_row[x] = tmax;
+  if (lane == 0) {
+    tau_row[x] = tmax;
+    if (capped && ncap > 0) atomicAdd(capped, static_cast<unsigned long long>(ncap));
+  }
 }
 
 // ------------------------------------------------------------------ CalTau (Algorithm 1)
@@ -84,7 +94,8 @@ __global__ __launch_bounds__(kThreads) void k_caltau(
     int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ deg, const double* __restrict__ lam,
     const double* __restrict__ phi, int omega, double eps_tau, int max_L,
-    int32_t* __restrict__ tau_slot, int32_t* __restrict__ tau_row) {
+    int32_t* __restrict__ tau_slot, int32_t* __restrict__ tau_row,
+    unsigned long long* __restrict__ capped) {
   constexpr int P = kMaxOmega / 64;
   const int x = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -104,6 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_caltau(
   const double shrink = 1.0 - lw * lw;
   const double log_inv = log(1.0 / lw);
   int tmax = 0;
+  int ncap = 0;   // slots of this row cut to max_L (same on every lane)
   for (int s = rowptr[x]; s < rowptr[x + 1]; ++s) {
     const int j = col[s];
     const double dj = static_cast<double>(deg[j]);
@@ -144,9 +156,13 @@ __global__ __launch_bounds__(kThreads) void k_caltau(
     }
     const int tau = t > max_L ? max_L : t;
     if (lane == 0) tau_slot[s] = tau;
+    ncap += t > max_L ? 1 : 0;
     tmax = tau > tmax ? tau : tmax;
   }
-  if (lane == 0) tau_row[x] = tmax;
+  if (lane == 0) {
+    tau_row[x] = tmax;
+    if (capped && ncap > 0) atomicAdd(capped, static_cast<unsigned long long>(ncap));
+  }
 }
 
 // Ritz vectors of the Lanczos basis: phi[x][1 + c] = sum_i V[i + 1][x] Y[i][c]
@@ -695,18 +711,19 @@ hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int i
 }
 
 hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
-                      int32_t* tau_slot, int32_t* tau_row, hipStream_t st) {
-  k_tau<<<grid_for(g.n, kWavesPerBlock), kThreads, 0, st>>>(g.n, g.rowptr, g.col, g.deg, L,
-                                                             eps_tau, lam, max_L, tau_slot, tau_row);
+                      int32_t* tau_slot, int32_t* tau_row, hipStream_t st,
+                      unsigned long long* capped) {
+  k_tau<<<grid_for(g.n, kWavesPerBlock), kThreads, 0, st>>>(
+      g.n, g.rowptr, g.col, g.deg, L, eps_tau, lam, max_L, tau_slot, tau_row, capped);
   return hipGetLastError();
 }
 
 hipError_t launch_caltau(const DeviceGraph& g, const double* lam, const double* phi, int omega,
                          double eps_tau, int max_L, int32_t* tau_slot, int32_t* tau_row,
-                         hipStream_t st) {
+                         hipStream_t st, unsigned long long* capped) {
   if (omega < 2 || omega > kMaxOmega) return hipErrorInvalidValue;
   k_caltau<<<grid_for(g.n, kWavesPerBlock), kThreads, 0, st>>>(
-      g.n, g.rowptr, g.col, g.deg, lam, phi, omega, eps_tau, max_L, tau_slot, tau_row);
+      g.n, g.rowptr, g.col, g.deg, lam, phi, omega, eps_tau, max_L, tau_slot, tau_row, capped);
   return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <limits>
 #include <chrono>
+#include <mutex>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -30,6 +32,48 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+namespace {
+std::mutex g_alloc_mu;
+std::unordered_map<void*, size_t> g_alloc_sizes;
+size_t g_alloc_live = 0;
+}  // namespace
+
+hipError_t tracked_malloc_bytes(void** p, size_t bytes) {
+  *p = nullptr;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (const char* lim = std::getenv("SC_DEVICE_BYTES_LIMIT")) {
+    const double cap = std::atof(lim);
+    if (cap > 0.0 && static_cast<double>(g_alloc_live) + static_cast<double>(bytes) > cap)
+      return hipErrorOutOfMemory;
+  }
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  g_alloc_sizes[*p] = bytes;
+  g_alloc_live += bytes;
+  return hipSuccess;
+}
+
+hipError_t tracked_free(void* p) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_alloc_sizes.find(p);
+    if (it != g_alloc_sizes.end()) {
+      g_alloc_live -= it->second;
+      g_alloc_sizes.erase(it);
+    }
+  }
+  return hipFree(p);
+}
+
+size_t tracked_live_bytes() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc_live;
+}
+
 }  // namespace sc
 
 using sc::dev_alloc;
@@ -50,7 +94,7 @@ void sc_graph::release() {
   dev_free(d.ptasks);
   dev_free(d.giant);
   for (auto& y : Y) {
-    if (y) (void)hipFree(y);
+    if (y) (void)sc::tracked_free(y);
     y = nullptr;
   }
   if (tail_stream) (void)hipStreamDestroy(tail_stream);
@@ -59,7 +103,7 @@ void sc_graph::release() {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
   }
-  if (partials) (void)hipFree(partials);
+  if (partials) (void)sc::tracked_free(partials);
   partials = nullptr;
   dev_free(mask);
   dev_free(anymask);
@@ -70,7 +114,7 @@ void sc_graph::release() {
   dev_free(spec_lam);
   dev_free(spec_phi);
   dev_free(cs);
-  if (colscratch) (void)hipFree(colscratch);
+  if (colscratch) (void)sc::tracked_free(colscratch);
   colscratch = nullptr;
   dev_free(work);
   dev_free(plan_work);
@@ -82,8 +126,8 @@ void sc_graph::release() {
   dev_free(out_dev);
   dev_free(tau_out_dev);
   dev_free(nr_out_dev);
-  if (rdiag) (void)hipFree(rdiag);
-  if (roff) (void)hipFree(roff);
+  if (rdiag) (void)sc::tracked_free(rdiag);
+  if (roff) (void)sc::tracked_free(roff);
   rdiag = roff = nullptr;
   rbytes = 0;
   dev_free(feat);
@@ -336,52 +380,6 @@ extern "C" void sc_free_graph(sc_graph* g) {
 
 namespace {
 
-// Cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major k x k).
-// On return a holds the eigenvalues on its diagonal and vec the eigenvectors (columns).
-void jacobi_eigen(std::vector<double>& a, std::vector<double>& vec, int k) {
-  vec.assign(static_cast<size_t>(k) * k, 0.0);
-  for (int i = 0; i < k; ++i) vec[static_cast<size_t>(i) * k + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int p = 0; p < k; ++p)
-      for (int q = 0; q < k; ++q) {
-        const double x = a[static_cast<size_t>(p) * k + q];
-        tot += x * x;
-        if (p != q) off += x * x;
-      }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = a[static_cast<size_t>(p) * k + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        const double app = a[static_cast<size_t>(p) * k + p];
-        const double aqq = a[static_cast<size_t>(q) * k + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0);
-        const double s = t * c;
-        for (int r = 0; r < k; ++r) {  // A <- A J (columns p, q)
-          const double arp = a[static_cast<size_t>(r) * k + p];
-          const double arq = a[static_cast<size_t>(r) * k + q];
-          a[static_cast<size_t>(r) * k + p] = c * arp - s * arq;
-          a[static_cast<size_t>(r) * k + q] = s * arp + c * arq;
-        }
-        for (int r = 0; r < k; ++r) {  // A <- J^T A (rows p, q)
-          const double apr = a[static_cast<size_t>(p) * k + r];
-          const double aqr = a[static_cast<size_t>(q) * k + r];
-          a[static_cast<size_t>(p) * k + r] = c * apr - s * aqr;
-          a[static_cast<size_t>(q) * k + r] = s * apr + c * aqr;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double vrp = vec[static_cast<size_t>(r) * k + p];
-          const double vrq = vec[static_cast<size_t>(r) * k + q];
-          vec[static_cast<size_t>(r) * k + p] = c * vrp - s * vrq;
-          vec[static_cast<size_t>(r) * k + q] = s * vrp + c * vrq;
-        }
-      }
-  }
-}
-
 __global__ void k_scale_into(const double* __restrict__ w, double s, double* __restrict__ dst,
                              int64_t n) {
   const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -392,7 +390,7 @@ __global__ void k_scale_into(const double* __restrict__ w, double s, double* __r
 // eigenvector sqrt(d / 2m) (eigenvalue 1, deflated by the re-orthogonalisation),
 // column 1 a fixed pseudo-random unit vector orthogonal to it; sid = 1/sqrt(d).
 hipError_t lanczos_start(const sc::DeviceGraph& dg, const int32_t* deg_host, double* V, int64_t ld,
-                         double* sid, hipStream_t st) {
+                         double* sid, hipStream_t st, uint64_t seed = 0) {
   const int64_t n = dg.n;
   std::vector<double> hv(n), sidh(n);
   const double two_m = static_cast<double>(dg.nslots);
@@ -401,7 +399,7 @@ hipError_t lanczos_start(const sc::DeviceGraph& dg, const int32_t* deg_host, dou
     sidh[x] = 1.0 / std::sqrt(static_cast<double>(deg_host[x]));
   }
   std::vector<double> v0(n);
-  uint64_t z = 0x9E3779B97F4A7C15ull;
+  uint64_t z = 0x9E3779B97F4A7C15ull * (2 * seed + 1);
   double dot = 0.0;
   for (int64_t x = 0; x < n; ++x) {
     z += 0x9E3779B97F4A7C15ull;
@@ -502,42 +500,53 @@ bool tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<do
   return true;
 }
 
-// extreme Ritz estimate: max over the two ends of |theta| + residual
+// extreme Ritz estimate: max over the two ends of |theta| + residual, where the
+// residual of a Ritz pair is |beta_last * (last component of its vector)|
+// (eigenvalues and last components by implicit QL, O(k^2) per check)
 double ritz_bound(const std::vector<double>& alpha, const std::vector<double>& beta, int k,
                   double beta_last, double* worst_res) {
-  std::vector<double> a(static_cast<size_t>(k) * k, 0.0), vec;
-  for (int i = 0; i < k; ++i) {
-    a[static_cast<size_t>(i) * k + i] = alpha[i];
-    if (i + 1 < k) {
-      a[static_cast<size_t>(i) * k + i + 1] = beta[i];
-      a[static_cast<size_t>(i + 1) * k + i] = beta[i];
-    }
+  std::vector<double> d(alpha.begin(), alpha.begin() + k), zl;
+  std::vector<double> e(beta.begin(), beta.begin() + std::min<size_t>(beta.size(), k));
+  if (!tridiag_eigen(d, e, nullptr, &zl)) {
+    *worst_res = 1.0;   // no answer: report as unconverged
+    return 1.0;
   }
-  jacobi_eigen(a, vec, k);
   int imax = 0, imin = 0;
   for (int i = 1; i < k; ++i) {
-    if (a[static_cast<size_t>(i) * k + i] > a[static_cast<size_t>(imax) * k + imax]) imax = i;
-    if (a[static_cast<size_t>(i) * k + i] < a[static_cast<size_t>(imin) * k + imin]) imin = i;
+    if (d[i] > d[imax]) imax = i;
+    if (d[i] < d[imin]) imin = i;
   }
-  const double rmax = std::fabs(beta_last * vec[static_cast<size_t>(k - 1) * k + imax]);
-  const double rmin = std::fabs(beta_last * vec[static_cast<size_t>(k - 1) * k + imin]);
-  const double tmax = a[static_cast<size_t>(imax) * k + imax];
-  const double tmin = a[static_cast<size_t>(imin) * k + imin];
+  const double rmax = std::fabs(beta_last * zl[imax]);
+  const double rmin = std::fabs(beta_last * zl[imin]);
   *worst_res = std::max(rmax, rmin);
-  return std::max(std::fabs(tmax) + rmax, std::fabs(tmin) + rmin);
+  return std::max(std::fabs(d[imax]) + rmax, std::fabs(d[imin]) + rmin);
 }
 
 }  // namespace
 
 int sc::compute_lambda_star(sc_graph* g, hipStream_t st, double* out) {
-  return lanczos_lambda_star(g->d, g->deg_h.data(), st, out);
+  // two Lanczos runs from independent start vectors; the larger estimate is kept
+  // (a start vector nearly orthogonal to the extreme eigenvector would make one
+  // run under-estimate), converged only if both runs passed the residual test
+  double a = 0.0, b = 0.0;
+  int ca = 0, cb = 0;
+  int rc = lanczos_lambda_star(g->d, g->deg_h.data(), st, &a, &ca, 0);
+  if (rc != SC_OK) return rc;
+  rc = lanczos_lambda_star(g->d, g->deg_h.data(), st, &b, &cb, 1);
+  if (rc != SC_OK) return rc;
+  *out = std::max(a, b);
+  g->lambda_converged = (ca && cb) ? 1 : 0;
+  return SC_OK;
 }
 
 int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipStream_t st,
-                            double* out) {
+                            double* out, int* converged, uint64_t seed) {
   using namespace sc;
   const int64_t n = dg.n;
-  const int kmax = static_cast<int>(std::min<int64_t>(n - 1, 160));
+  // up to 600 steps, the basis held to 4 GiB
+  const int64_t kcap = std::max<int64_t>(40, (int64_t(1) << 29) / std::max<int64_t>(n, 1) - 2);
+  const int kmax = static_cast<int>(std::min<int64_t>({n - 1, 600, kcap}));
+  if (converged) *converged = 0;
   const int64_t ld = n;
   double *V = nullptr, *w = nullptr, *h = nullptr, *sid = nullptr;
   auto cleanup = [&]() {
@@ -555,7 +564,7 @@ int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipS
     cleanup();
     return fail(e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP, "lanczos allocation failed");
   }
-  HIP_TRY(lanczos_start(dg, deg_host, V, ld, sid, st));
+  HIP_TRY(lanczos_start(dg, deg_host, V, ld, sid, st, seed));
 
   std::vector<double> alpha, beta, hh(kmax + 2);
   double result = -1.0;
@@ -581,7 +590,11 @@ int sc::lanczos_lambda_star(const DeviceGraph& dg, const int32_t* deg_host, hipS
       double res = 0.0;
       const double bound = ritz_bound(alpha, beta, j, exhausted ? 0.0 : b_j, &res);
       result = bound;
-      if (exhausted || res < 1e-9) break;
+      if (b_j < 1e-12 || res < 1e-9) {   // Krylov space exhausted, or both ends converged
+        if (converged) *converged = 1;
+        break;
+      }
+      if (exhausted) break;
     }
     beta.push_back(b_j);
     k_scale_into<<<grid, 256, 0, st>>>(w, 1.0 / b_j, V + static_cast<size_t>(j + 1) * ld, n);
@@ -853,11 +866,11 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   const size_t yb = static_cast<size_t>(n) * B * tsize;
   if (yb > g->ybytes) {
     for (auto& y : g->Y) {
-      if (y) (void)hipFree(y);
+      if (y) (void)sc::tracked_free(y);
       y = nullptr;
     }
     g->ybytes = 0;
-    for (auto& y : g->Y) HIP_TRY(hipMalloc(&y, yb));
+    for (auto& y : g->Y) HIP_TRY(sc::tracked_malloc(&y, yb));
     g->ybytes = yb;
   }
   if (!g->nz) {
@@ -866,10 +879,10 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   }
   const size_t pb = static_cast<size_t>(std::max(g->d.nparts, 1)) * B * tsize;
   if (pb > g->pbytes) {
-    if (g->partials) (void)hipFree(g->partials);
+    if (g->partials) (void)sc::tracked_free(g->partials);
     g->partials = nullptr;
     g->pbytes = 0;
-    HIP_TRY(hipMalloc(&g->partials, pb));
+    HIP_TRY(sc::tracked_malloc(&g->partials, pb));
     g->pbytes = pb;
   }
   if (!g->mask) {
@@ -884,8 +897,8 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   if (!g->tau_row) HIP_TRY(dev_alloc(&g->tau_row, n));
   if (!g->nr_slot) HIP_TRY(dev_alloc(&g->nr_slot, S));
   if (!g->cs) HIP_TRY(dev_alloc(&g->cs, 64));
-  if (!g->colscratch) HIP_TRY(hipMalloc(&g->colscratch, sc::kColScratchBytes));
-  if (!g->work) HIP_TRY(dev_alloc(&g->work, 2));
+  if (!g->colscratch) HIP_TRY(sc::tracked_malloc(&g->colscratch, sc::kColScratchBytes));
+  if (!g->work) HIP_TRY(dev_alloc(&g->work, 4));   // [0..1] walk totals, [2] capped halves
   if (!g->plan_work) HIP_TRY(dev_alloc(&g->plan_work, 2 * 64));
   if (!g->out_dev) HIP_TRY(dev_alloc(&g->out_dev, g->d.m));
   return SC_OK;
@@ -952,7 +965,15 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   Runner<T> R{g, B, st, (o.flags & SC_TIME_KERNELS) != 0};
   R.stats.block = B;
   R.stats.tilde_tau = -1;
-  hipEvent_t t0, t1;
+  R.stats.tilde_min = -1;
+  R.stats.tilde_max = -1;
+  R.stats.lambda_converged = -1;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  auto destroy_events = [&]() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+  const sc::ScopeExit<decltype(destroy_events)> ev_guard{destroy_events};   // every return path
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
   HIP_TRY(hipEventRecord(t0, st));
@@ -974,19 +995,25 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     } else {
       rc = sc::graph_lambda_star(g, st, &lam);
       if (rc) return rc;
+      R.stats.lambda_converged = g->lambda_converged;
     }
     if (!(lam > 0.0 && lam < 1.0)) return fail(SC_EINVAL, "lambda* must lie in (0, 1)");
   }
   R.stats.lambda_star = lam;
   const double eps_tau = plus ? eps / 2.0 : eps;
+  unsigned long long* capped = g->work + 2;
+  HIP_TRY(hipMemsetAsync(capped, 0, sizeof(unsigned long long), st));
   if (spectral)
     HIP_TRY(sc::launch_caltau(g->d, g->spec_lam, g->spec_phi, g->spec_omega, eps_tau, max_L,
-                              g->tau_slot, g->tau_row, st));
+                              g->tau_slot, g->tau_row, st, capped));
   else
-    HIP_TRY(sc::launch_tau(g->d, Lodd, eps_tau, lam, max_L, g->tau_slot, g->tau_row, st));
+    HIP_TRY(sc::launch_tau(g->d, Lodd, eps_tau, lam, max_L, g->tau_slot, g->tau_row, st, capped));
   std::vector<int32_t> tau_row(n);
+  unsigned long long capped_h = 0;
   HIP_TRY(hipMemcpyAsync(tau_row.data(), g->tau_row, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&capped_h, capped, sizeof(capped_h), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  R.stats.L_capped = static_cast<int64_t>(capped_h / 2);   // both halves of an edge share tau
   int Lmax = 0, Lmin = 1 << 30;
   for (int64_t x = 0; x < n; ++x) {
     Lmax = std::max(Lmax, tau_row[x]);
@@ -1081,6 +1108,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
       g->plan_valid = true;
     }
     R.stats.tilde_tau = tilde;
+    R.stats.tilde_min = tilde;
+    R.stats.tilde_max = tilde;
   }
   HIP_TRY(sc::launch_gacc_init(g->d, g->tau_slot, (plus && tilde < 1) ? 0 : 1, g->gacc, st));
   R.ev_used = 0;
@@ -1197,8 +1226,6 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   HIP_TRY(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   R.stats.total_ms = ms;
   R.stats.walks = plus ? static_cast<int64_t>(wk[0]) : 0;
   R.stats.walk_steps = plus ? static_cast<int64_t>(wk[1]) : 0;

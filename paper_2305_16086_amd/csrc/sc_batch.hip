@@ -59,8 +59,9 @@ struct sc_batch {
   int64_t* d_edge_off = nullptr;   // [G + 1]
   sc::BatchItem* d_items = nullptr;
   size_t items_cap = 0;
-  int32_t* d_misc = nullptr;       // [0, kLaunchMax): tickets; [kLaunchMax, +2): tau min / max
-  int32_t* h_misc = nullptr;       // pinned copy of the tau range
+  int32_t* d_misc = nullptr;       // [0, kLaunchMax): tickets; [kLaunchMax, +2): tau min / max;
+                                   // [kLaunchMax + 2, +2): capped half-edges (one 64-bit word)
+  int32_t* h_misc = nullptr;       // pinned copy of the tau range and the capped count
   void* slabs = nullptr;
   size_t slab_bytes = 0;
   size_t lds_budget = 0;
@@ -105,7 +106,7 @@ struct sc_batch {
     sc::dev_free(d_edge_off);
     sc::dev_free(d_items);
     sc::dev_free(d_misc);
-    if (slabs) (void)hipFree(slabs);
+    if (slabs) (void)sc::tracked_free(slabs);
     slabs = nullptr;
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
@@ -241,6 +242,8 @@ struct Plan {
   std::vector<int> graphs;             // subset, in batch order
   std::vector<int> L;                  // odd L per graph of the subset (0 = automatic)
   std::vector<double> lam;             // lambda* per graph of the subset (automatic only)
+  std::vector<int> spectral;           // 1: CalTau with the graph's spectrum (automatic only)
+  std::vector<int> spec_version;       // the spectrum's version when spectral
   std::vector<int> block;              // B per graph of the subset
   std::vector<int> threads;            // workgroup size per graph (0: class default)
   std::vector<sc::BatchItem> items;    // grouped by launch
@@ -262,6 +265,8 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
   const size_t ng = subset.size();
   P.L.resize(ng);
   P.lam.assign(ng, 0.0);
+  P.spectral.assign(ng, 0);
+  P.spec_version.assign(ng, 0);
   P.block.resize(ng);
   P.threads.assign(ng, 0);
   std::vector<double> est(ng);
@@ -281,6 +286,16 @@ int plan_run(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     if (Lg > 0) {
       P.L[q] = (Lg % 2 == 1) ? Lg : Lg + 1;
       est[q] = P.L[q];
+    } else if ((o.flags & SC_TAU_SPECTRAL) && g->spec_omega >= 2) {
+      // CalTau (Algorithm 1) with the graph's own spectrum; lam = |lambda_omega| for the
+      // cost estimate only
+      P.L[q] = 0;
+      P.spectral[q] = 1;
+      P.spec_version[q] = g->spec_version;
+      P.lam[q] = std::fabs(g->spec_lam_h[1]);
+      const double lam = std::max(1e-3, std::min(P.lam[q], 0.999999));
+      const double t = std::ceil(std::log(1.0 / (eps * (1.0 - lam * lam))) / std::log(1.0 / lam));
+      est[q] = std::min<double>(P.max_L, std::max(1.0, t));
     } else {
       double lam = o.lambda_star;
       if (!(lam > 0.0)) {
@@ -401,7 +416,7 @@ int stage_plan(sc_batch* b, const Plan& P, double* const* outs) {
   for (size_t q = 0; q < P.graphs.size(); ++q) {
     sc::BatchGraph& d = tab[P.graphs[q]];
     d.B = P.block[q];
-    d.L = P.L[q];
+    d.L = P.spectral[q] ? -1 : P.L[q];   // -1: tau written by CalTau before the prologue
     d.lam = P.lam[q];
     d.out = outs[q];
     d.active = 1;
@@ -421,10 +436,10 @@ int stage_plan(sc_batch* b, const Plan& P, double* const* outs) {
   if (slab_grid > 0) {
     const size_t need = static_cast<size_t>(slab_grid) * P.slab_elems * tsize;
     if (need > b->slab_bytes) {
-      if (b->slabs) (void)hipFree(b->slabs);
+      if (b->slabs) (void)sc::tracked_free(b->slabs);
       b->slabs = nullptr;
       b->slab_bytes = 0;
-      HIP_TRY(hipMalloc(&b->slabs, need));
+      HIP_TRY(sc::tracked_malloc(&b->slabs, need));
       b->slab_bytes = need;
     }
   }
@@ -433,17 +448,26 @@ int stage_plan(sc_batch* b, const Plan& P, double* const* outs) {
 
 // Device work of plan P on stream st (no allocation, no host synchronisation,
 // no memset: safe to capture).  outs[q]: device output of graph P.graphs[q].
+// The tau range and the capped count are always computed, so a recorded graph
+// serves runs with and without statistics alike.
 template <typename T>
-int enqueue_run(sc_batch* b, const Plan& P, hipStream_t st, hipEvent_t kb, hipEvent_t ke,
-                bool want_range) {
+int enqueue_run(sc_batch* b, const Plan& P, hipStream_t st, hipEvent_t kb, hipEvent_t ke) {
   const int G = static_cast<int>(b->graphs.size());
-  int32_t* mm = want_range ? b->d_misc + kLaunchMax : nullptr;
+  int32_t* mm = b->d_misc + kLaunchMax;
+  auto* capped = reinterpret_cast<unsigned long long*>(b->d_misc + kLaunchMax + 2);
   HIP_TRY(sc::launch_fill_i32(b->d_misc, kLaunchMax, 0, st));
-  if (mm) {
-    HIP_TRY(sc::launch_fill_i32(mm, 1, INT32_MAX, st));
-    HIP_TRY(sc::launch_fill_i32(mm + 1, 1, 0, st));
+  HIP_TRY(sc::launch_fill_i32(mm, 1, INT32_MAX, st));
+  HIP_TRY(sc::launch_fill_i32(mm + 1, 3, 0, st));   // tau max and the 64-bit capped count
+  for (size_t q = 0; q < P.graphs.size(); ++q) {
+    if (!P.spectral[q]) continue;
+    const int gi = P.graphs[q];
+    const sc_graph* g = b->graphs[gi];
+    HIP_TRY(sc::launch_caltau(g->d, g->spec_lam, g->spec_phi, g->spec_omega, P.eps, P.max_L,
+                              b->tau_slot + b->slot_off[gi], b->tau_row + b->node_off[gi], st,
+                              capped));
   }
-  HIP_TRY(sc::launch_batch_prologue(b->d_graphs, b->d_node_off, G, b->node_off[G], mm, st));
+  HIP_TRY(sc::launch_batch_prologue(b->d_graphs, b->d_node_off, G, b->node_off[G], mm, capped,
+                                    st));
   if (kb) HIP_TRY(hipEventRecord(kb, st));
   for (size_t li = 0; li < P.launches.size(); ++li) {
     const Launch& l = P.launches[li];
@@ -467,8 +491,9 @@ std::string run_key(const Plan& P, const sc_options& o, double* const* outs, boo
   for (size_t q = 0; q < P.graphs.size(); ++q) {
     uint64_t lb;
     std::memcpy(&lb, &P.lam[q], sizeof(lb));
-    std::snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%" PRIx64 ",%p;", P.graphs[q], P.L[q], P.block[q],
-                  P.threads[q], lb, host_out ? nullptr : static_cast<void*>(outs[q]));
+    std::snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%" PRIx64 ",%d,%p;", P.graphs[q], P.L[q],
+                  P.block[q], P.threads[q], lb, P.spectral[q] ? P.spec_version[q] : -1,
+                  host_out ? nullptr : static_cast<void*>(outs[q]));
     k += buf;
   }
   return k;
@@ -519,7 +544,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     if (!reuse) {
       // record on the batch's own stream; the graph is then launched on st
       HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
-      rc = enqueue_run<T>(b, P, b->cap_stream, nullptr, nullptr, want_range);
+      rc = enqueue_run<T>(b, P, b->cap_stream, nullptr, nullptr);
       if (!dev_ptrs && rc == SC_OK) {
         for (int gi : P.graphs) {
           const hipError_t e = hipMemcpyAsync(
@@ -548,7 +573,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     }
     HIP_TRY(hipGraphLaunch(b->exec, st));
   } else {
-    rc = enqueue_run<T>(b, P, st, kb, ke, want_range);
+    rc = enqueue_run<T>(b, P, st, kb, ke);
     if (rc) return rc;
     if (!dev_ptrs)
       for (int gi : P.graphs)
@@ -556,7 +581,7 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
                                b->graphs[gi]->d.m * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   if (want_range)
-    HIP_TRY(hipMemcpyAsync(b->h_misc, b->d_misc + kLaunchMax, 2 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(b->h_misc, b->d_misc + kLaunchMax, 4 * sizeof(int32_t),
                            hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(t1, st));
   if (!dev_ptrs || want_range || timing) HIP_TRY(hipEventSynchronize(t1));
@@ -570,7 +595,13 @@ int run_batch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
     sc_stats s{};
     s.L_used = b->h_misc[1];
     s.L_min = b->h_misc[0];
+    unsigned long long capped_h = 0;
+    std::memcpy(&capped_h, b->h_misc + 2, sizeof(capped_h));
+    s.L_capped = static_cast<int64_t>(capped_h / 2);   // both halves of an edge share tau
     s.tilde_tau = -1;
+    s.tilde_min = -1;
+    s.tilde_max = -1;
+    s.lambda_converged = -1;
     int B0 = P.block.empty() ? 0 : P.block[0];
     for (int B : P.block)
       if (B != B0) B0 = -1;
@@ -594,8 +625,6 @@ int run_dispatch(sc_batch* b, double eps, const int32_t* L, const sc_options& o,
                  double* const* out, sc_stats* st, float* kernel_ms) {
   if (!(eps > 0.0 && eps < 1.0)) return fail(SC_EINVAL, "eps must lie in (0, 1)");
   if (o.method != SC_TGT) return fail(SC_ENOTIMPL, "batches run TGT (method 0) only");
-  if (o.flags & SC_TAU_SPECTRAL)
-    return fail(SC_ENOTIMPL, "batches use the lambda*-bound (SC_TAU_SPECTRAL not supported)");
   if (o.precision != 0 && o.precision != 1) return fail(SC_EINVAL, "precision must be 0 or 1");
   if (o.block != 0 && !valid_block(o.block))
     return fail(SC_EINVAL, "batch block must be 0 or 1, 2, 4, 8, 16, 32, 64");
@@ -673,7 +702,7 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
   if (e == hipSuccess) e = sc::dev_alloc(&b->out_dev, b->edge_off[G]);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->out_pinned),
                                          std::max<int64_t>(1, b->edge_off[G]) * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_misc), 2 * sizeof(int32_t));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_misc), 4 * sizeof(int32_t));
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_graphs, G);
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_node_off, G + 1);
   if (e == hipSuccess)
@@ -681,7 +710,7 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
   if (e == hipSuccess) e = sc::dev_alloc(&b->d_edge_off, G + 1);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_edge_off, b->edge_off.data(), (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = sc::dev_alloc(&b->d_misc, kLaunchMax + 2);
+  if (e == hipSuccess) e = sc::dev_alloc(&b->d_misc, kLaunchMax + 4);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   int lds = 0, cus = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);

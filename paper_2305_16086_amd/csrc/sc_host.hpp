@@ -12,16 +12,33 @@ namespace sc {
 // Records the message for sc_last_error() and returns code.
 int fail(int code, const std::string& msg);
 
+// Every device allocation of the library goes through these two calls, which
+// keep the live byte count.  When the environment variable
+// SC_DEVICE_BYTES_LIMIT holds a positive number, an allocation that would
+// take the live bytes above it fails with hipErrorOutOfMemory (a device-memory
+// budget; also how the out-of-memory paths are tested).
+hipError_t tracked_malloc_bytes(void** p, size_t bytes);
+hipError_t tracked_free(void* p);
+size_t tracked_live_bytes();
+
+template <typename P>
+hipError_t tracked_malloc(P** p, size_t bytes) {
+  void* q = nullptr;
+  const hipError_t e = tracked_malloc_bytes(&q, bytes);
+  *p = static_cast<P*>(q);
+  return e;
+}
+
 template <typename P>
 hipError_t dev_alloc(P** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(P));
+  return tracked_malloc(p, count * sizeof(P));
 }
 
 template <typename P>
 void dev_free(P*& p) {
-  if (p) (void)hipFree(p);
+  if (p) (void)tracked_free(p);
   p = nullptr;
 }
 
@@ -53,6 +70,7 @@ struct sc_graph {
   std::vector<int32_t> rowptr_h;
   std::vector<int32_t> deg_h;
   double lambda_star = -1.0;
+  int lambda_converged = -1;            // of the cached lambda* (see sc_stats)
   // spectrum for CalTau (Algorithm 1): spec_omega eigenpairs of D^-1/2 A D^-1/2,
   // |lambda| descending after the trivial pair; phi node-major [n][spec_omega]
   int spec_omega = 0;
@@ -138,7 +156,10 @@ int build_host_csr(int64_t n, int64_t m, const int64_t* u, const int64_t* v, uns
 int upload_csr(const HostCSR& h, DeviceGraph& d);
 // New handle owning an upload of h (h.rowptr and h.deg are moved into it).
 int graph_from_csr(HostCSR& h, sc_graph** out);
-int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out);
+// One Lanczos run from start vector number `seed`; *converged = 1 when the
+// extreme Ritz pairs passed the residual test (or the Krylov space closed).
+int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out,
+                        int* converged = nullptr, uint64_t seed = 0);
 // Lanczos for the omega eigenpairs of largest |lambda| (stores the converged prefix in g)
 int lanczos_spectrum(sc_graph* g, int omega, int max_iter, double tol, hipStream_t st, int* kept,
                      double* worst);

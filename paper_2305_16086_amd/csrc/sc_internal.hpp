@@ -118,7 +118,8 @@ struct BatchGraph {
   const int32_t* half_slot = nullptr;
   double* out = nullptr;            // device output, m doubles
   int32_t m = 0;
-  int32_t L = 0;                    // odd uniform truncation, or 0: Theorem 3.2
+  int32_t L = 0;                    // odd uniform truncation, 0: Theorem 3.2, -1: tau_slot
+                                    // and tau_row already hold CalTau's lengths
   int32_t max_L = 0;
   int32_t active = 0;               // 1: graph takes part in the run
   double eps = 0.0;
@@ -149,16 +150,18 @@ hipError_t launch_gacc_init(const DeviceGraph& g, const int32_t* tau_slot, int i
 // D^-1/2 A D^-1/2 of largest |lambda| (lam[omega], phi[n][omega] node-major on
 // the device, pair 0 the trivial one); tau capped at the odd max_L.
 constexpr int kMaxOmega = 256;
+// capped (may be null): += half-edges whose automatic tau was cut to max_L.
 hipError_t launch_caltau(const DeviceGraph& g, const double* lam, const double* phi, int omega,
                          double eps_tau, int max_L, int32_t* tau_slot, int32_t* tau_row,
-                         hipStream_t st);
+                         hipStream_t st, unsigned long long* capped = nullptr);
 // Ritz vectors phi[x][1..p] = V[:, 1..steps] Y (Y: steps x p32 row-major, p32 a multiple of
 // kRitzCols), phi[x][0] = V[x]
 constexpr int kRitzCols = 32;
 hipError_t launch_ritz(int64_t n, int64_t ld, const double* V, int steps, const double* Y,
                        int p32, int p, int omega, double* phi, hipStream_t st);
 hipError_t launch_tau(const DeviceGraph& g, int L, double eps_tau, double lam, int max_L,
-                      int32_t* tau_slot, int32_t* tau_row, hipStream_t st);
+                      int32_t* tau_slot, int32_t* tau_row, hipStream_t st,
+                      unsigned long long* capped = nullptr);
 
 // Mark block s_set's neighbour bits in mask buffer `buf` and clear block
 // s_clear's bits (s_clear < 0: none) in the other buffer.  mask: 2 x n words,
@@ -326,9 +329,11 @@ const void* batch_kernel_ptr(int nt, bool lds, int B);
 hipError_t launch_fill_i32(int32_t* p, int count, int value, hipStream_t st);
 // Truncation per slot and row, and the closed-form l = 0, 1 terms, for every
 // row of the active graphs (node_off: G + 1 prefix of node counts); with mm,
-// mm[0] / mm[1] take the min / max of the rows' truncations.
+// mm[0] / mm[1] take the min / max of the rows' truncations; capped (may be
+// null) += half-edges whose automatic length was cut to max_L.
 hipError_t launch_batch_prologue(const BatchGraph* graphs, const int64_t* node_off, int G,
-                                 int64_t total_rows, int32_t* mm, hipStream_t st);
+                                 int64_t total_rows, int32_t* mm, unsigned long long* capped,
+                                 hipStream_t st);
 // out[e] = g(u_e, v_e) + g(v_e, u_e) for every edge of the active graphs.
 hipError_t launch_batch_combine(const BatchGraph* graphs, const int64_t* edge_off, int G,
                                 int64_t total_edges, hipStream_t st);

@@ -3,6 +3,7 @@
 // SC_LEARNED run with its certified fallback.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -251,18 +252,99 @@ extern "C" int sc_mlp_predict(const sc_mlp* net, const float* X, int64_t N, int 
   return SC_OK;
 }
 
+// ====================================================================== weights file
+//
+// Layout (little-endian): 8-byte magic "SCMLPW01", u32 parameter count (5313),
+// u32 flags (bit 0: normalisation set, bit 1: feature range set), then
+// float32 params[5313], norm[32], range[32], then the u64 FNV-1a hash of every
+// byte before it.
+
+namespace {
+
+constexpr char kMagic[8] = {'S', 'C', 'M', 'L', 'P', 'W', '0', '1'};
+
+uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+constexpr size_t kFileBytes = 8 + 4 + 4 + sizeof(float) * (kP + 64) + 8;
+
+}  // namespace
+
+extern "C" int sc_mlp_save(const sc_mlp* net, const char* path) {
+  if (!net || !path) return fail(SC_EINVAL, "net or path is NULL");
+  std::vector<unsigned char> buf(kFileBytes);
+  std::vector<float> vals(kP + 64);
+  const int rc = sc_mlp_get(net, vals.data(), vals.data() + kP, vals.data() + kP + 32);
+  if (rc != SC_OK) return rc;
+  const uint32_t count = kP;
+  const uint32_t flags = (net->has_norm ? 1u : 0u) | (net->has_range ? 2u : 0u);
+  unsigned char* p = buf.data();
+  std::memcpy(p, kMagic, 8);
+  std::memcpy(p + 8, &count, 4);
+  std::memcpy(p + 12, &flags, 4);
+  std::memcpy(p + 16, vals.data(), sizeof(float) * vals.size());
+  const uint64_t h = fnv1a(buf.data(), kFileBytes - 8);
+  std::memcpy(p + kFileBytes - 8, &h, 8);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SC_EINVAL, std::string("cannot open for writing: ") + path);
+  const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
+  const int c = std::fclose(f);
+  if (w != buf.size() || c != 0) return fail(SC_EINVAL, std::string("write failed: ") + path);
+  return SC_OK;
+}
+
+extern "C" int sc_mlp_load(const char* path, sc_mlp** out) {
+  if (!path || !out) return fail(SC_EINVAL, "path or out is NULL");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SC_EINVAL, std::string("cannot open: ") + path);
+  std::vector<unsigned char> buf(kFileBytes + 1);
+  const size_t r = std::fread(buf.data(), 1, buf.size(), f);
+  std::fclose(f);
+  if (r != kFileBytes) return fail(SC_EINVAL, std::string("not a weights file (size): ") + path);
+  uint32_t count = 0, flags = 0;
+  uint64_t h = 0;
+  std::memcpy(&count, buf.data() + 8, 4);
+  std::memcpy(&flags, buf.data() + 12, 4);
+  std::memcpy(&h, buf.data() + kFileBytes - 8, 8);
+  if (std::memcmp(buf.data(), kMagic, 8) != 0 || count != static_cast<uint32_t>(kP) || (flags & ~3u))
+    return fail(SC_EINVAL, std::string("not a weights file (header): ") + path);
+  if (fnv1a(buf.data(), kFileBytes - 8) != h)
+    return fail(SC_EINVAL, std::string("weights file corrupted (checksum): ") + path);
+  std::vector<float> vals(kP + 64);
+  std::memcpy(vals.data(), buf.data() + 16, sizeof(float) * vals.size());
+  for (float x : vals)
+    if (std::isnan(x)) return fail(SC_EINVAL, std::string("weights file holds NaN: ") + path);
+  sc_mlp* net = nullptr;
+  int rc = sc_mlp_create(0, &net);
+  if (rc != SC_OK) return rc;
+  rc = sc_mlp_set(net, vals.data(), (flags & 1u) ? vals.data() + kP : nullptr,
+                  (flags & 2u) ? vals.data() + kP + 32 : nullptr);
+  if (rc != SC_OK) {
+    sc_mlp_free(net);
+    return rc;
+  }
+  *out = net;
+  return SC_OK;
+}
+
 // ====================================================================== closure data and run
 
 int sc::ensure_closure_buffers(sc_graph* g, size_t tsize) {
   const int64_t S = g->d.nslots, m = g->d.m;
   const size_t rb = static_cast<size_t>(S) * (kRecSteps + 1) * tsize;
   if (rb > g->rbytes) {
-    if (g->rdiag) (void)hipFree(g->rdiag);
-    if (g->roff) (void)hipFree(g->roff);
+    if (g->rdiag) (void)sc::tracked_free(g->rdiag);
+    if (g->roff) (void)sc::tracked_free(g->roff);
     g->rdiag = g->roff = nullptr;
     g->rbytes = 0;
-    HIP_TRY(hipMalloc(&g->rdiag, rb));
-    HIP_TRY(hipMalloc(&g->roff, rb));
+    HIP_TRY(sc::tracked_malloc(&g->rdiag, rb));
+    HIP_TRY(sc::tracked_malloc(&g->roff, rb));
     g->rbytes = rb;
   }
   if (!g->feat) HIP_TRY(dev_alloc(&g->feat, static_cast<size_t>(m) * kFeat));

@@ -17,13 +17,18 @@ __device__ inline int odd_at_least(double f) {
 
 // L > 0: the uniform odd L.  Else Theorem 3.2 with Upsilon = Delta = 0 (Eq. 6):
 // the smallest odd tau with lam^(tau+1) (1/d_i + 1/d_j - 2/(d_i d_j)) /
-// (1 - lam^2) <= eps_tau, capped at max_L.
-__device__ inline int tau_of(int L, double di, double dj, double eps_tau, double lam, int max_L) {
+// (1 - lam^2) <= eps_tau, not yet capped.
+__device__ inline int tau_uncapped(int L, double di, double dj, double eps_tau, double lam) {
   if (L > 0) return L;
   const double num = 1.0 / di + 1.0 / dj - 2.0 / (di * dj);
   const double f = ceil(log(num / (eps_tau * (1.0 - lam * lam))) / log(1.0 / lam) - 1.0);
-  const int t = odd_at_least(f);
-  return t > max_L ? max_L : t;
+  return odd_at_least(f);
+}
+
+// As tau_uncapped, capped at max_L (automatic lengths only; a fixed L is the caller's).
+__device__ inline int tau_of(int L, double di, double dj, double eps_tau, double lam, int max_L) {
+  const int t = tau_uncapped(L, di, dj, eps_tau, lam);
+  return (L <= 0 && t > max_L) ? max_L : t;
 }
 
 }  // namespace sc

@@ -85,6 +85,12 @@ class ScStats(C.Structure):
         ("fallback_edges", C.c_int64),
         ("prop_timed", C.c_int64),
         ("host_ms", C.c_double),
+        ("L_capped", C.c_int64),
+        ("lambda_converged", C.c_int32),
+        ("tilde_min", C.c_int32),
+        ("tilde_max", C.c_int32),
+        ("reserved_", C.c_int32),
+        ("push_edges", C.c_int64),
     ]
 
     def as_dict(self):
@@ -140,6 +146,10 @@ def _load():
     lib.sc_mlp_get.restype = C.c_int
     lib.sc_mlp_set.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.sc_mlp_set.restype = C.c_int
+    lib.sc_mlp_save.argtypes = [C.c_void_p, C.c_char_p]
+    lib.sc_mlp_save.restype = C.c_int
+    lib.sc_mlp_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+    lib.sc_mlp_load.restype = C.c_int
     lib.sc_closure_dataset.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p]
     lib.sc_closure_dataset.restype = C.c_int
@@ -187,7 +197,8 @@ EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_gr
             "sc_closure_features", "sc_mlp_train", "sc_mlp_grad", "sc_mlp_predict",
             "sc_build_batch", "sc_batch_size", "sc_batch_graph", "sc_free_batch",
             "sc_batch_all_edges", "sc_batch_blocks", "sc_batch_autotune", "sc_batch_load_tuning",
-            "sc_compute_spectrum", "sc_set_spectrum", "sc_get_spectrum"]
+            "sc_compute_spectrum", "sc_set_spectrum", "sc_get_spectrum", "sc_mlp_save",
+            "sc_mlp_load"]
 
 
 def _check(rc, where):
@@ -440,6 +451,16 @@ def sc_mlp_set(net: Mlp, params=None, norm=None, range_=None):
     na, npp = arr(norm, 32)
     ra, rp = arr(range_, 32)
     _check(_lib.sc_mlp_set(net.handle, pp, npp, rp), "sc_mlp_set")
+
+
+def sc_mlp_save(net: Mlp, path: str):
+    _check(_lib.sc_mlp_save(net.handle, os.fsencode(path)), "sc_mlp_save")
+
+
+def sc_mlp_load(path: str) -> Mlp:
+    h = C.c_void_p()
+    _check(_lib.sc_mlp_load(os.fsencode(path), C.byref(h)), "sc_mlp_load")
+    return Mlp(h)
 
 
 def sc_closure_dataset(g: Graph, L_ref: int, precision: int, X, z, w):
