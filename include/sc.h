@@ -64,6 +64,10 @@ enum {
 #define SC_TAU_SPECTRAL 0x10u /* automatic truncation (L = 0) by CalTau, Algorithm 1, with
                                  the graph's spectrum (sc_compute_spectrum / sc_set_spectrum)
                                  instead of the lambda*-bound; SC_TGT and SC_TGT_PLUS */
+#define SC_PER_SOURCE 0x20u   /* SC_TGT_PLUS only: Algorithm 4 source by source, each with a
+                                 frontier-sparse traversal and its own switch step by Eq. 14
+                                 (Section 4.2.1), instead of dense blocks of sources with one
+                                 switch step per call; see sc_all_edges_ex */
 
 /* methods (sc_options.method) */
 #define SC_TGT 0       /* Algorithm 2: traversal to tau for every source */
@@ -94,6 +98,14 @@ typedef struct sc_options {
   const sc_mlp* mlp;       /* trained network (required)                              */
   int infer_bf16;          /* 1: BF16 MFMA inference (default), 0: FP32               */
   int force_fallback;      /* 1: every edge takes the fallback traversal              */
+  /* SC_PER_SOURCE only */
+  const int32_t* sources;  /* host list of nsources distinct source nodes, or NULL for all;
+                              only the halves (i, j) with i listed are computed, so out[e]
+                              is the full estimate only where both endpoints are listed
+                              (the others hold the l = 0 term of an unlisted half)      */
+  int64_t nsources;
+  int switch_rule;         /* 0: Eq. 14 as printed (frontier volume against walk pairs);
+                              1: against single-walk steps, 2 (tau_ij - l) per pair      */
 } sc_options;
 
 typedef struct sc_stats {
@@ -224,6 +236,21 @@ int sc_all_edges(sc_graph* g, double eps, int L, double* out);
  */
 int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double* out,
                     sc_stats* st);
+/*
+ * With SC_PER_SOURCE (TGT+): every source i starts at p_0(., i) = e_i and,
+ * at l = 0, 1, ..., tests Eq. 14: the volume of the nodes with p_l(v, i) != 0
+ * against the walk pairs (switch_rule 0) or walk steps (1) that stopping at l
+ * would need (Eq. 13 with chi of Algorithm 3 at q = p_l(., i)); the first l
+ * where the volume is larger, or l = max_j tau_ij, is tilde_tau_i (recorded in
+ * tilde_tau_out).  Steps are pushed over the support only.  tilde_tau >= 0 in
+ * the options forces min(tilde_tau, max_j tau_ij) for every source instead.
+ * Any gamma >= 0 is accepted.  The traversal keeps 64-bit fixed-point columns
+ * (unit 2^-63) and sums them with integer atomics, so results are
+ * reproducible; precision and block are ignored.  Per-source columns take
+ * 24 n bytes per workgroup slot (up to 2048 slots, within a third of the free
+ * device memory or SC_SOURCE_SLOT_BYTES).  st: tilde_min / tilde_max,
+ * push_edges, walks, walk_steps.
+ */
 
 /* ------------------------------------------------------------------ learned closure
  *

@@ -207,12 +207,10 @@ def rho_hat(g, q, gamma):
     rho_i when the best edge has one endpoint outside C.)"""
     C = top_candidates(q, gamma)
     bound = q[C[0]] + q[C[-1]]
-    best = -np.inf
-    for a_pos in range(len(C)):
-        for b_pos in range(a_pos + 1, len(C)):
-            a, b = C[a_pos], C[b_pos]
-            if g.adjacent(a, b):
-                best = max(best, q[a] + q[b])
+    in_c = np.zeros(g.n, dtype=bool)
+    in_c[C] = True
+    both = in_c[g.u] & in_c[g.v]          # the edges of C x C
+    best = float(np.max(q[g.u[both]] + q[g.v[both]])) if both.any() else -np.inf
     return max(best, bound)
 
 
@@ -243,6 +241,9 @@ def chi_value(g, q, i, j, length, gamma, rho=None):
     lbi, ubi = walk_bounds(g, q, i, length, rho)
     lbj, ubj = walk_bounds(g, q, j, length, rho)
     return ubi + ubj - lbi - lbj
+
+
+NR_CAP = 2 ** 31 - 1   # walk pairs per half-edge are capped (a reading: counts fit 31 bits)
 
 
 def walk_count(chi, deg_i, eps, m, delta):
@@ -333,3 +334,67 @@ def tgt_plus_replay(g, tau_edge, tilde_tau, nr_uv, nr_vu, seed, sources=None):
                 acc[k] += xs.mean()
         gh[H] = acc
     return gh[: g.m], gh[g.m:], gh[: g.m] + gh[g.m:]
+
+
+# ------------------------------------------------------------------ per-source switch (Eq. 14)
+
+def switch_step(g, i, tau_half_i, eps, delta, gamma, rule=0, trace=None):
+    """Algorithm 4 lines 3-11 for source i with the adaptive switch of Section
+    4.2.1: starting at l = 0 with p_0(., i) = e_i, stop at the first l where
+    Eq. 14 holds,
+
+        sum of d(v) over the nodes with p_l(v, i) != 0
+            >  sum over the halves (i, j) of R(e_ij, tau_ij - l),
+
+    R from Eq. 13 with chi from Algorithm 3 at q = p_l(., i) (n_r = 0 where
+    tau_ij - l <= 0, so the loop also ends at l = max_j tau_ij); otherwise push
+    one step and continue.  rule = 1 weighs each walk pair by its
+    2 (tau_ij - l) single-walk steps (the right-hand side then counts walk
+    steps, not walk pairs).  ``tau_half_i`` lists tau_ij over the halves of i in
+    the order of ``g.halves_of([i])``.  Returns (tilde_tau, n_r per half of i);
+    ``trace`` (a list) receives (l, left side, right side) per test."""
+    g = as_graph(g)
+    H = g.halves_of([i])
+    hj = g.hdst[H]
+    tau_h = np.asarray(tau_half_i, dtype=np.int64)
+    x = np.zeros(g.n)
+    x[i] = 1.0
+    ell = 0
+    while True:
+        lhs = float(g.degf[x != 0].sum())
+        nr = np.zeros(len(H), dtype=np.int64)
+        live = tau_h - ell > 0
+        if live.any():
+            rho = rho_hat(g, x, gamma) if gamma > 0 else None
+            for k in np.nonzero(live)[0]:
+                length = int(tau_h[k] - ell)
+                chi = chi_value(g, x, i, int(hj[k]), length, gamma, rho)
+                nr[k] = min(walk_count(chi, g.degf[i], eps, g.m, delta), NR_CAP)
+        rhs = float(nr.sum()) if rule == 0 else float((2 * nr * np.maximum(tau_h - ell, 0)).sum())
+        if trace is not None:
+            trace.append((ell, lhs, rhs))
+        if lhs > rhs:
+            return ell, nr
+        x = g.P @ x
+        ell += 1
+
+
+def tgt_plus_adaptive(g, tau_edge, eps, delta, gamma, seed, rule=0, sources=None):
+    """Algorithm 4 with a switch step per source by Eq. 14 (``switch_step``):
+    the decisions (tilde_tau per source, n_r per half-edge) are taken first and
+    the estimate is then ``tgt_plus_replay`` with them.  Returns
+    (s, tilde_tau[n], nr_uv, nr_vu) with -1 / 0 for sources not computed."""
+    g = as_graph(g)
+    tau_edge = np.asarray(tau_edge, dtype=np.int64)
+    tau_half = np.concatenate([tau_edge, tau_edge])
+    tilde = np.full(g.n, -1, dtype=np.int64)
+    nr = np.zeros(2 * g.m, dtype=np.int64)
+    src = range(g.n) if sources is None else [int(x) for x in sources]
+    for i in src:
+        H = g.halves_of([i])
+        if len(H) == 0:
+            continue
+        tilde[i], nr[H] = switch_step(g, i, tau_half[H], eps, delta, gamma, rule)
+    tt = np.where(tilde < 0, 0, tilde)
+    _, _, s = tgt_plus_replay(g, tau_edge, tt, nr[: g.m], nr[g.m:], seed, sources=sources)
+    return s, tilde, nr[: g.m], nr[g.m:]

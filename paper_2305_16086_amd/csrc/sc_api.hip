@@ -128,6 +128,20 @@ void sc_graph::release() {
   dev_free(nr_out_dev);
   if (rdiag) (void)sc::tracked_free(rdiag);
   if (roff) (void)sc::tracked_free(roff);
+  sc::dev_free(src.Q);
+  sc::dev_free(src.S);
+  sc::dev_free(src.slot_ctl);
+  sc::dev_free(src.tilde_row);
+  sc::dev_free(src.pos_slot);
+  sc::dev_free(src.pos_w);
+  sc::dev_free(src.nr_pos);
+  sc::dev_free(src.chunk_off);
+  sc::dev_free(src.part);
+  sc::dev_free(src.ctl);
+  sc::dev_free(src.totals);
+  sc::dev_free(src.list);
+  sc::dev_free(src.hoff);
+  src = SourceBuffers{};
   rdiag = roff = nullptr;
   rbytes = 0;
   dev_free(feat);
@@ -855,6 +869,9 @@ extern "C" void sc_default_options(sc_options* o) {
   o->mlp = nullptr;
   o->infer_bf16 = 1;
   o->force_fallback = 0;
+  o->sources = nullptr;
+  o->nsources = 0;
+  o->switch_rule = 0;
 }
 
 namespace sc {
@@ -1264,8 +1281,14 @@ extern "C" int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options*
   if (cur != g->device) (void)hipSetDevice(g->device);
   if (opt.method == SC_LEARNED && (opt.flags & SC_TAU_SPECTRAL))
     return fail(SC_ENOTIMPL, "SC_TAU_SPECTRAL is not supported with SC_LEARNED");
+  const bool per_source = (opt.flags & SC_PER_SOURCE) != 0;
+  if (per_source && opt.method != SC_TGT_PLUS)
+    return fail(SC_ENOTIMPL, "SC_PER_SOURCE runs TGT+ (method 1) only");
+  if (opt.sources && !per_source) return fail(SC_EINVAL, "a source list needs SC_PER_SOURCE");
   int rc;
-  if (opt.method == SC_LEARNED)
+  if (per_source)
+    rc = sc::run_per_source(g, eps, L, opt, out, st);
+  else if (opt.method == SC_LEARNED)
     rc = sc::run_learned(g, eps, opt, out, st);
   else
     rc = opt.precision == 1 ? run_method<double>(g, eps, L, opt, out, st)

@@ -120,6 +120,35 @@ struct sc_graph {
   PlanKey plan_key{};
   int plan_tilde = -1;
   bool plan_valid = false;
+  // per-source TGT+ (SC_PER_SOURCE): workgroup-slot columns and the wave buffers
+  struct SourceBuffers {
+    uint64_t* Q = nullptr;          // [2 * slots * n] 64-bit fixed-point columns
+    int32_t* S = nullptr;           // [2 * slots * n] support lists
+    size_t qcap = 0;
+    bool clean = false;             // Q is all zero (every call that finished leaves it so)
+    int32_t* slot_ctl = nullptr;
+    size_t ctl_cap = 0;
+    int32_t* tilde_row = nullptr;
+    size_t tilde_cap = 0;
+    int32_t* pos_slot = nullptr;
+    size_t pos_cap = 0;
+    int32_t* pos_w = nullptr;
+    size_t posw_cap = 0;
+    int64_t* nr_pos = nullptr;
+    size_t nrp_cap = 0;
+    int64_t* chunk_off = nullptr;
+    size_t co_cap = 0;
+    double* part = nullptr;
+    size_t part_cap = 0;
+    int64_t* ctl = nullptr;
+    size_t ctl2_cap = 0;
+    unsigned long long* totals = nullptr;
+    size_t tot_cap = 0;
+    int32_t* list = nullptr;
+    size_t list_cap = 0;
+    int64_t* hoff = nullptr;
+    size_t hoff_cap = 0;
+  } src;
   double* out_dev = nullptr;
   int32_t* tau_out_dev = nullptr;
   int64_t* nr_out_dev = nullptr;
@@ -158,6 +187,11 @@ int upload_csr(const HostCSR& h, DeviceGraph& d);
 int graph_from_csr(HostCSR& h, sc_graph** out);
 // One Lanczos run from start vector number `seed`; *converged = 1 when the
 // extreme Ritz pairs passed the residual test (or the Krylov space closed).
+// TGT+ with the frontier-sparse traversal and the per-source switch step of
+// Eq. 14 (SC_PER_SOURCE).
+int run_per_source(sc_graph* g, double eps, int L, const sc_options& o, double* out,
+                   sc_stats* st);
+
 int lanczos_lambda_star(const DeviceGraph& d, const int32_t* deg_host, hipStream_t st, double* out,
                         int* converged = nullptr, uint64_t seed = 0);
 // Lanczos for the omega eigenpairs of largest |lambda| (stores the converged prefix in g)

@@ -268,6 +268,68 @@ hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,
 hipError_t launch_trace(const DeviceGraph& g, const int32_t* tau_slot, const int64_t* nr_slot,
                         int32_t* tau_out, int64_t* nr_out, hipStream_t st);
 
+// --------------------------------------------------------------- per-source TGT+
+// Frontier-sparse traversal with the per-source switch step of Eq. 14, one
+// workgroup per source (kernels_sparse.hip).  Columns are 64-bit fixed point
+// Q[y] = p_l(i, y) / d_y in units of 2^-63, one pair of n-word columns and one
+// pair of n-entry support lists per workgroup slot.
+constexpr int kSrcThreads = 256;
+
+struct SrcArgs {
+  int32_t n = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const int32_t* tau_slot = nullptr;
+  const int32_t* tau_row = nullptr;
+  const int32_t* srcs = nullptr;   // source list (null: node k is entry k)
+  const int64_t* hoff = nullptr;   // [nsrc + 1] prefix of the listed sources' degrees (null: rowptr)
+  int64_t list_base = 0;           // first list entry of this launch (workgroup w takes entry base + w)
+  int64_t nsrc = 0;                // list length
+  int64_t pos_base = 0;            // hoff[list_base]: positions are relative to it
+  uint64_t* Q = nullptr;           // [2 * slots * n], all zero between sources
+  int32_t* S = nullptr;            // [2 * slots * n]
+  int32_t* slot_ctl = nullptr;     // [2 * slots]: final support size, which column holds it
+  int32_t* tilde_row = nullptr;    // [n] switch step per source
+  int64_t* nr_slot = nullptr;      // [2m] walk pairs per CSR slot
+  double* gacc = nullptr;          // [2m] per-half sums (l = 0 term already in)
+  int32_t* pos_slot = nullptr;     // [positions] CSR slot of each position
+  int32_t* pos_w = nullptr;        // [positions] workgroup slot holding its source's column
+  int64_t* nr_pos = nullptr;       // [positions] walk pairs
+  unsigned long long* totals = nullptr;   // walk pairs, walk steps, pushed entries, min / max tilde
+  double coef = 0.0;               // 8 ln(2m / delta) / eps^2 (Eq. 13)
+  int64_t nr_cap = 0;
+  int gamma = 10;
+  int rule = 0;                    // 0: Eq. 14 as printed (walk pairs), 1: walk steps
+  int force_tilde = -1;            // >= 0: switch at min(force_tilde, tau_p) instead
+};
+
+struct SrcWalkArgs {
+  int32_t n = 0;
+  int64_t P = 0;                   // positions of this wave
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const int32_t* slot_row = nullptr;
+  const int32_t* tau_slot = nullptr;
+  const int32_t* tilde_row = nullptr;
+  const uint64_t* Q = nullptr;
+  uint64_t* Qw = nullptr;          // same memory, cleared after the walks
+  const int32_t* S = nullptr;
+  const int32_t* slot_ctl = nullptr;
+  const int32_t* pos_slot = nullptr;
+  const int32_t* pos_w = nullptr;
+  const int64_t* nr_pos = nullptr;
+  int64_t* chunk_off = nullptr;    // [P + 1]
+  int64_t* ctl = nullptr;          // [2]
+  double* part = nullptr;          // [capacity]
+  int64_t capacity = 0;
+  double* gacc = nullptr;
+  unsigned k0 = 0, k1 = 0;         // Philox key
+};
+
+hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st);
+// scan, walks, finish and the clearing of the wave's columns
+hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st);
+
 // --------------------------------------------------------------- learned closure
 constexpr int kMlpParams = 5313;
 constexpr int kFeat = 16;

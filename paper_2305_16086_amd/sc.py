@@ -30,6 +30,7 @@ SC_DEVICE_PTRS = 0x1
 SC_TIME_KERNELS = 0x4
 SC_GRAPH_REPLAY = 0x8
 SC_TAU_SPECTRAL = 0x10
+SC_PER_SOURCE = 0x20
 
 SC_TGT = 0
 SC_TGT_PLUS = 1
@@ -56,6 +57,9 @@ class ScOptions(C.Structure):
         ("mlp", C.c_void_p),
         ("infer_bf16", C.c_int),
         ("force_fallback", C.c_int),
+        ("sources", C.c_void_p),
+        ("nsources", C.c_int64),
+        ("switch_rule", C.c_int),
     ]
 
 
@@ -335,11 +339,18 @@ def _ptr(x):
 
 
 def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = None, out=None,
-                    tau_out=None, tilde_tau_out=None, nr_out=None):
+                    tau_out=None, tilde_tau_out=None, nr_out=None, sources=None):
     """Run with explicit options.  ``out`` and the trace arrays are numpy arrays
     (host) or torch CUDA tensors (then SC_DEVICE_PTRS is set and the current
-    torch stream is used unless options.stream is set).  Returns (out, stats dict)."""
+    torch stream is used unless options.stream is set).  ``sources`` (host
+    int32 ids, SC_PER_SOURCE only) restricts the computed halves to those
+    sources.  Returns (out, stats dict)."""
     o = options if options is not None else sc_default_options()
+    src_arr = None
+    if sources is not None:
+        src_arr = np.ascontiguousarray(sources, dtype=np.int32)
+        o.sources = src_arr.ctypes.data
+        o.nsources = len(src_arr)
     device = out is not None and not isinstance(out, np.ndarray)
     if out is None:
         out = np.empty(g.m, dtype=np.float64)

@@ -80,15 +80,15 @@ def test_lambda_converged_is_minus_one_when_given(sc):
     g.free()
 
 
-@pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("max_L", [3, 7, 255])
+# TGT+ only with short caps: the grid's walk counts at long truncations are huge
+@pytest.mark.parametrize("method,max_L", [(0, 3), (0, 7), (0, 255), (1, 3), (1, 7)])
 def test_L_capped_counts_cut_edges(sc, method, max_L):
     n, u, v = gg.king_grid(400)
     eps = 1e-2
     print(f"[gpu] L_capped king400 method={method} max_L={max_L}", flush=True)
     g = sc.sc_build_graph(n, u, v)
     tau = np.empty(len(u), np.int32)
-    o = sc.sc_default_options(method=method, max_L=max_L, tilde_tau=2)
+    o = sc.sc_default_options(method=method, max_L=max_L)
     _, st = sc.sc_all_edges_ex(g, eps, 0, o, tau_out=tau)
     lam = st["lambda_star"]
     g.free()

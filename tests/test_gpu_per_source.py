@@ -1,0 +1,264 @@
+"""GPU parity of per-source TGT+ (SC_PER_SOURCE): Algorithm 4 with a
+frontier-sparse traversal and the switch step of Eq. 14 decided per source.
+
+* the switch step of every source equal to the oracle's Eq. 14 decision
+  (oracle.tgt.switch_step), except where the two sides of Eq. 14 are within
+  the one-walk rounding of Eq. 13's ceiling; the walk counts within one walk;
+* the estimate against the oracle's replay (Algorithm 4 with the GPU's
+  tilde_tau and n_r, the same Philox walks): 1e-12 (the traversal runs in
+  64-bit fixed point, the oracle in float64);
+* within eps of the exact SC;
+* a forced uniform switch step: the same walk counts and estimates as the
+  dense block path at that switch step (up to n_r ceilings);
+* gamma from 0 to beyond n, both switch rules, hub rows, source subsets,
+  many waves of workgroup slots, the walk-per-half fallback, determinism,
+  error paths.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import exact as ex
+from oracle import tgt as otgt
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_16086_amd import sc as scmod
+    return scmod
+
+
+def run_ps(sc, graph, eps, L=0, sources=None, g=None, **opt):
+    n, u, v = graph
+    print(f"[gpu] per-source n={n} m={len(u)} eps={eps} L={L} opt={opt} "
+          f"sources={None if sources is None else len(sources)}", flush=True)
+    own = g is None
+    if own:
+        g = sc.sc_build_graph(n, u, v)
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, seed=77, **opt)
+    tau = np.empty(len(u), np.int32)
+    tt = np.empty(n, np.int32)
+    nr = np.empty(2 * len(u), np.int64)
+    out, st = sc.sc_all_edges_ex(g, eps, L, o, tau_out=tau, tilde_tau_out=tt, nr_out=nr,
+                                 sources=sources)
+    if own:
+        g.free()
+    return out, st, tau, tt, nr
+
+
+def check_against_oracle(graph, eps, out, st, tau, tt, nr, gamma=10, rule=0, sources=None,
+                         check_switch=True):
+    n, u, v = graph
+    m = len(u)
+    G = otgt.Graph(n, u, v)
+    src = np.arange(n) if sources is None else np.asarray(sources)
+    # replay with the GPU's decisions: same walks, so only rounding differs
+    _, _, ref = otgt.tgt_plus_replay(G, tau, np.where(tt < 0, 0, tt), nr[:m], nr[m:], seed=77,
+                                     sources=src)
+    if sources is None:
+        np.testing.assert_allclose(out, ref, atol=TOL, rtol=0)
+    if not check_switch:
+        return
+    # Eq. 14 per source, and the walk counts at the GPU's switch step
+    delta = 1.0 / n
+    tau_half = np.concatenate([tau, tau]).astype(np.int64)
+    mism = 0
+    for i in src:
+        H = G.halves_of([int(i)])
+        trace = []
+        t_or, nr_or = otgt.switch_step(G, int(i), tau_half[H], eps, delta, gamma, rule, trace)
+        if t_or != tt[i]:
+            mism += 1
+            # only a near tie may differ: each n_r can move by one at a ceiling
+            l, lhs, rhs = trace[min(tt[i], t_or)]
+            slack = len(H) * (1 if rule == 0 else 2 * int(tau_half[H].max()))
+            assert abs(lhs - rhs) <= slack, (i, tt[i], t_or, trace)
+            continue
+        assert np.all(np.abs(nr[H] - nr_or) <= 1), (i, nr[H], nr_or)
+    assert mism <= max(1, len(src) // 100)
+
+
+GRAPHS = {
+    "tree_gnp": lambda: gg.tree_plus_gnp(300, 8.0, 5),
+    "ba": lambda: gg.barabasi_albert(400, 4, 6),
+    "king": lambda: gg.king_grid(200),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("eps", [0.05, 0.02])
+def test_eq14_switch_and_replay(sc, name, eps):
+    graph = GRAPHS[name]()
+    n, u, v = graph
+    out, st, tau, tt, nr = run_ps(sc, graph, eps, max_L=31)
+    assert st["tilde_min"] == tt.min() and st["tilde_max"] == tt.max()
+    check_against_oracle(graph, eps, out, st, tau, tt, nr)
+    if st["L_capped"] == 0:
+        assert np.abs(out - ex.sc_pinv(n, u, v)).max() <= eps
+
+
+@pytest.mark.parametrize("gamma", [0, 1, 3, 40, 1000])
+def test_gamma_range(sc, gamma):
+    graph = gg.barabasi_albert(250, 3, 9)
+    out, st, tau, tt, nr = run_ps(sc, graph, 0.03, gamma=gamma)
+    check_against_oracle(graph, 0.03, out, st, tau, tt, nr, gamma=gamma)
+
+
+def test_step_rule(sc):
+    graph = gg.tree_plus_gnp(250, 7.0, 4)
+    out0, st0, tau, tt0, nr0 = run_ps(sc, graph, 0.03, switch_rule=0)
+    out1, st1, tau1, tt1, nr1 = run_ps(sc, graph, 0.03, switch_rule=1)
+    np.testing.assert_array_equal(tau, tau1)
+    assert np.all(tt1 >= tt0)
+    check_against_oracle(graph, 0.03, out1, st1, tau1, tt1, nr1, rule=1)
+
+
+@pytest.mark.parametrize("name", ["petersen", "k5", "c7", "triangle_pendant"])
+def test_tiny_graphs(sc, name):
+    graph = {"petersen": gg.petersen_graph, "k5": lambda: gg.complete_graph(5),
+             "c7": lambda: gg.cycle_graph(7), "triangle_pendant": gg.triangle_pendant}[name]()
+    n, u, v = graph
+    for gamma in (0, 2, 10):
+        out, st, tau, tt, nr = run_ps(sc, graph, 0.1, gamma=gamma, lambda_star=0.9)
+        check_against_oracle(graph, 0.1, out, st, tau, tt, nr, gamma=gamma)
+
+
+@pytest.mark.parametrize("tilde", [0, 1, 2, 3])
+def test_forced_switch_matches_dense_path(sc, tilde):
+    graph = gg.tree_plus_gnp(120, 8.0, 3)   # small: low switch steps mean many walks to replay
+    n, u, v = graph
+    eps = 0.1
+    out, st, tau, tt, nr = run_ps(sc, graph, eps, tilde_tau=tilde)
+    taup = np.zeros(n, np.int64)
+    np.maximum.at(taup, u, tau)
+    np.maximum.at(taup, v, tau)
+    np.testing.assert_array_equal(tt, np.minimum(tilde, taup))
+    # the dense path at the same switch step: the same walks (Philox counters)
+    g = sc.sc_build_graph(n, u, v)
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, precision=1, tilde_tau=tilde, seed=77)
+    nr_d = np.empty(2 * len(u), np.int64)
+    tt_d = np.empty(n, np.int32)
+    out_d, _ = sc.sc_all_edges_ex(g, eps, 0, o, nr_out=nr_d, tilde_tau_out=tt_d)
+    g.free()
+    same = nr == nr_d
+    assert same.mean() >= 0.999
+    check_against_oracle(graph, eps, out, st, tau, tt, nr, check_switch=False)
+    if same.all():
+        np.testing.assert_allclose(out, out_d, atol=TOL, rtol=0)
+
+
+def test_hub_rows(sc):
+    # a BA graph plus a hub joined to 3,000 nodes: pushes and scans of one long list
+    n, u, v = gg.barabasi_albert(4000, 3, 2)
+    hub = 0
+    extra = np.arange(1, 3001)
+    eu = np.concatenate([u, np.full(len(extra), hub)])
+    ev = np.concatenate([v, extra])
+    uu, vv = gg.canonical_edges(n, eu, ev)
+    graph = (n, uu, vv)
+    src = np.concatenate([[hub], np.arange(1, 4000, 97)])
+    out, st, tau, tt, nr = run_ps(sc, graph, 0.05, sources=src.astype(np.int32))
+    check_against_oracle(graph, 0.05, out, st, tau, tt, nr, sources=src)
+    m = len(uu)
+    G = otgt.Graph(n, uu, vv)
+    _, _, ref = otgt.tgt_plus_replay(G, tau, np.where(tt < 0, 0, tt), nr[:m], nr[m:], seed=77,
+                                     sources=src)
+    both = np.isin(uu, src) & np.isin(vv, src)
+    np.testing.assert_allclose(out[both], ref[both], atol=TOL, rtol=0)
+
+
+def test_source_subset_equals_full_run(sc):
+    graph = gg.barabasi_albert(600, 4, 12)
+    n, u, v = graph
+    full, _, tau, tt, nr = run_ps(sc, graph, 0.03)
+    rng = np.random.default_rng(1)
+    src = np.sort(rng.choice(n, 200, replace=False)).astype(np.int32)
+    part, _, tau2, tt2, nr2 = run_ps(sc, graph, 0.03, sources=src[::-1].copy())
+    m = len(u)
+    both = np.isin(u, src) & np.isin(v, src)
+    np.testing.assert_array_equal(part[both], full[both])
+    listed = np.zeros(n, bool)
+    listed[src] = True
+    np.testing.assert_array_equal(tt2[listed], tt[listed])
+    assert np.all(tt2[~listed] == -1)
+    hl = np.concatenate([listed[u], listed[v]])
+    np.testing.assert_array_equal(nr2[hl], nr[hl])
+    assert np.all(nr2[~hl] == 0)
+
+
+def test_many_waves_and_walk_fallback_agree(sc, monkeypatch):
+    graph = gg.tree_plus_gnp(500, 8.0, 8)
+    ref, _, _, tt, nr = run_ps(sc, graph, 0.03)
+    monkeypatch.setenv("SC_SOURCE_SLOT_BYTES", str(7 * 500 * 24))   # 7 workgroup slots
+    out, st, _, tt2, nr2 = run_ps(sc, graph, 0.03)
+    np.testing.assert_array_equal(out, ref)
+    np.testing.assert_array_equal(tt2, tt)
+    monkeypatch.setenv("SC_SOURCE_PART_CAPACITY", "1")            # walks one half per wave
+    out3, _, _, _, nr3 = run_ps(sc, graph, 0.03)
+    np.testing.assert_array_equal(nr3, nr)
+    np.testing.assert_allclose(out3, ref, atol=TOL, rtol=0)
+
+
+def test_deterministic(sc):
+    graph = gg.barabasi_albert(800, 5, 3)
+    a, _, _, _, _ = run_ps(sc, graph, 0.02)
+    b, _, _, _, _ = run_ps(sc, graph, 0.02)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_ba100k_sampled(sc):
+    import os
+    graph = gg.workload("ba_100k", 1)
+    n, u, v = graph
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "ba_100k_seed1_sampled_sc.npz"))
+    ids, exact = gold["edge_ids"], gold["sc"]
+    out, st, tau, tt, nr = run_ps(sc, graph, 1e-3)
+    print(f"[gpu] ba_100k per-source: tilde {st['tilde_min']}..{st['tilde_max']} walks {st['walks']} "
+          f"push {st['push_edges']} ms {st['total_ms']:.1f}", flush=True)
+    assert st["L_capped"] == 0
+    assert np.abs(out[ids] - exact).max() <= 1e-3
+    # replay of a few sources' halves against the oracle
+    m = len(u)
+    G = otgt.Graph(n, u, v)
+    src = np.array([5, 999, 54321, 99999])
+    g_uv, g_vu, _ = otgt.tgt_plus_replay(G, tau, np.where(tt < 0, 0, tt), nr[:m], nr[m:],
+                                         seed=77, sources=src)
+    g = sc.sc_build_graph(n, u, v)
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, seed=77)
+    half, _ = sc.sc_all_edges_ex(g, 1e-3, 0, o, sources=src.astype(np.int32))
+    g.free()
+    # halves of listed sources: out = g(u, v) + (l = 0 term of the unlisted half)
+    du = np.bincount(np.concatenate([u, v]), minlength=n).astype(float)
+    for arr_src, mask, gh, other in ((u, np.isin(u, src) & ~np.isin(v, src), g_uv, v),
+                                     (v, np.isin(v, src) & ~np.isin(u, src), g_vu, u)):
+        np.testing.assert_allclose(half[mask], gh[mask] + 1.0 / du[other[mask]], atol=TOL, rtol=0)
+
+
+def test_errors(sc):
+    n, u, v = gg.barabasi_albert(100, 3, 1)
+    g = sc.sc_build_graph(n, u, v)
+    with pytest.raises(sc.ScError) as e:
+        sc.sc_all_edges_ex(g, 0.05, 0, sc.sc_default_options(method=sc.SC_TGT,
+                                                             flags=sc.SC_PER_SOURCE))
+    assert e.value.code == sc.SC_ENOTIMPL
+    with pytest.raises(sc.ScError) as e:
+        sc.sc_all_edges_ex(g, 0.05, 0, sc.sc_default_options(method=sc.SC_TGT_PLUS),
+                           sources=np.array([1, 2], np.int32))
+    assert e.value.code == sc.SC_EINVAL
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE)
+    out = np.full(len(u), 3.0)
+    for bad in (np.array([1, 1], np.int32), np.array([-1], np.int32), np.array([n], np.int32)):
+        with pytest.raises(sc.ScError) as e:
+            sc.sc_all_edges_ex(g, 0.05, 0, o, out=out, sources=bad)
+        assert e.value.code == sc.SC_EINVAL
+    assert np.all(out == 3.0)
+    o.switch_rule = 2
+    with pytest.raises(sc.ScError):
+        sc.sc_all_edges_ex(g, 0.05, 0, o)
+    g.free()
