@@ -564,7 +564,65 @@ __global__ __launch_bounds__(256) void k_src_clear(int n, int nslots_used, uint6
   for (int e = threadIdx.x; e < cnt; e += 256) Qs[Ss[e]] = 0;
 }
 
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, int64_t count,
+                                                  uint64_t value) {
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < count;
+       k += static_cast<int64_t>(gridDim.x) * 256)
+    p[k] = value;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
+                                                  uint32_t value) {
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < count;
+       k += static_cast<int64_t>(gridDim.x) * 256)
+    p[k] = value;
+}
+
+// smallest and largest row truncation (tau_row) into mm[0] / mm[1]
+__global__ __launch_bounds__(256) void k_tau_range(int n, const int32_t* __restrict__ tau_row,
+                                                   unsigned long long* __restrict__ mm) {
+  unsigned long long lo = ~0ull, hi = 0;
+  for (int x = blockIdx.x * 256 + threadIdx.x; x < n; x += gridDim.x * 256) {
+    const unsigned long long t = static_cast<unsigned long long>(tau_row[x]);
+    lo = t < lo ? t : lo;
+    hi = t > hi ? t : hi;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long a = __shfl_xor(lo, off, 64);
+    const unsigned long long b = __shfl_xor(hi, off, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+  }
+}
+
+inline unsigned fill_grid(int64_t count) {
+  const int64_t g = (count + 255) / 256;
+  return static_cast<unsigned>(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
 }  // namespace
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_fill_u64<<<fill_grid(count), 256, 0, st>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_fill_u32<<<fill_grid(count), 256, 0, st>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_tau_range(int n, const int32_t* tau_row, unsigned long long* mm, hipStream_t st) {
+  k_tau_range<<<fill_grid(n) < 1024 ? fill_grid(n) : 1024, 256, 0, st>>>(n, tau_row, mm);
+  return hipGetLastError();
+}
 
 hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st) {
   if (grid <= 0) return hipSuccess;

@@ -97,3 +97,20 @@ def test_planted_mistake_is_caught():
     minv = np.linalg.inv(lap + 1.0 / n)
     wrong = minv[u, u] + minv[v, v] + 2.0 * minv[u, v]
     assert np.abs(wrong - s_enum).max() > 1e-3
+
+
+def test_batch_golden_matches_pseudoinverse_on_small_graphs():
+    """The stored sampled SC of the 256-graph batch (written by
+    tests/golden/make_batch_oracle.py from the oracle's block-PCG) agrees with
+    the dense pseudoinverse on the smallest graph of each family."""
+    import os
+    import graphgen as gg
+    gz = np.load(os.path.join(os.path.dirname(__file__), "golden", "batch_256_seed7_sampled_sc.npz"))
+    graphs = gg.workload("batch_256", 7)
+    assert len(np.unique(gz["graph"])) == 256
+    for fam in range(3):
+        k = min((i for i in range(256) if i % 3 == fam), key=lambda i: graphs[i][0])
+        n, u, v = graphs[k]
+        sel = gz["graph"] == k
+        np.testing.assert_allclose(gz["sc"][sel], ex.sc_pinv(n, u, v)[gz["edge_ids"][sel]],
+                                   atol=1e-9, rtol=0)
