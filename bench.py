@@ -59,7 +59,7 @@ def parse():
     p.add_argument("--cpu-sources", type=int, default=1500,
                    help="sources in the CPU-baseline sample (about 10-15 s of CPU work)")
     p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau",
-                                      "params"],
+                                      "params", "rmat"],
                    default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
                         "persistent launch against one graph at a time; learned: the "
@@ -72,6 +72,9 @@ def parse():
     p.add_argument("--check-edges", type=int, default=16,
                    help="er/eps: sampled edges checked against exact SC (conjugate gradients)")
     p.add_argument("--replay", action="store_true", help="batch: replay a captured hipGraph")
+    p.add_argument("--rmat-scale", type=int, default=22, help="rmat: R-MAT scale")
+    p.add_argument("--rmat-sources", type=int, default=4096,
+                   help="rmat: uniform random sources timed (the full call is extrapolated)")
     p.add_argument("--no-extras", action="store_true",
                    help="plain: skip the comparison forms carried in the line (learned closure, "
                         "TGT+ at eps=1e-5, per-source TGT+, the 256-graph batch)")
@@ -625,7 +628,8 @@ def params_form(a):
             dt, st = timed_calls(sc, g, eps, o, out, a.steps, a.warmup)
             rows.append({"graph": name, "n": n, "m": m, "eps": eps, label: value,
                          "gamma": gamma, "ms": 1e3 * dt, "walks": st["walks"],
-                         "L_used": st["L_used"], "tilde_tau": st["tilde_tau"]})
+                         "L_used": st["L_used"], "tilde_tau": st["tilde_tau"],
+                         "tilde_min": st["tilde_min"], "tilde_max": st["tilde_max"]})
             print(f"[params] {name} {label}={value} gamma={gamma}: {1e3 * dt:.1f} ms, "
                   f"walks {st['walks']}, L {st['L_used']}, tilde {st['tilde_tau']}",
                   file=sys.stderr, flush=True)
@@ -639,6 +643,11 @@ def params_form(a):
                 point("omega", w, sc.SC_TAU_SPECTRAL, 10)
         for gamma in (0, 2, 5, 10, 16):
             point("gamma_sweep", gamma, 0, gamma)
+        if do_omega:
+            # the per-source path takes any gamma (top-gamma by radix select): Figure 5b's range
+            for gamma in (0, 10, 100, 1000, 10000):
+                if gamma <= n:
+                    point("gamma_per_source", gamma, sc.SC_PER_SOURCE, gamma)
         g.free()
     head = [r for r in rows if r["graph"] == "ba_100k" and r.get("gamma_sweep") == 10][0]
     line = {
@@ -758,6 +767,96 @@ def batch_summary(sc, stream):
             "one_at_a_time_tgt_plus_edges_per_s": M / one_s, "lambda_preprocess_s": pre_s}
 
 
+RMAT_GOLDEN = os.path.join(ROOT, "tests", "golden", "rmat22_seed22_sampled_sc.npz")
+
+
+def rmat_form(a):
+    """R-MAT scale 22 (a, b, c, d = .57, .19, .19, .05, edge factor 16, symmetrised,
+    deduplicated, largest component; seed 22) by per-source TGT+ (frontier-sparse
+    traversal, switch step by Eq. 14 per source) at eps = 1e-2.  A full call is
+    out of reach of the time budget here, so a uniform random sample of
+    --rmat-sources sources is timed (each source's halves are independent work)
+    and the call time is extrapolated by n / sample; the error is checked on the
+    512 sampled edges whose exact SC the oracle stored, by a second call over
+    their endpoints (both halves of every checked edge computed)."""
+    import torch
+    from paper_2305_16086_amd import sc
+    import graphgen as gg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    eps = 1e-2
+    t0 = time.perf_counter()
+    n, u, v = gg.rmat_lcc(a.rmat_scale, 16, seed=22)
+    m = len(u)
+    gen_s = time.perf_counter() - t0
+    print(f"[rmat] scale {a.rmat_scale}: n={n} m={m} ({gen_s:.0f} s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = sc.sc_build_graph(n, u, v)
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lam = sc.sc_lambda_star(g)
+    lam_s = time.perf_counter() - t0
+    print(f"[rmat] built {build_s:.1f} s, lambda* {lam:.4f} ({lam_s:.1f} s)", file=sys.stderr,
+          flush=True)
+    out = torch.empty(m, dtype=torch.float64, device=dev)
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, stream=stream.cuda_stream)
+    rng = np.random.default_rng(22)
+    src = rng.choice(n, size=min(a.rmat_sources, n), replace=False).astype(np.int32)
+    sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src[:256])   # buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    full_s = dt * n / len(src)
+    print(f"[rmat] {len(src)} sources in {dt:.2f} s -> full call {full_s:.0f} s; walks {st['walks']}, "
+          f"push {st['push_edges']}, tilde {st['tilde_min']}..{st['tilde_max']}", file=sys.stderr,
+          flush=True)
+    err = None
+    checked = 0
+    ck = {}
+    if a.rmat_scale == 22 and os.path.exists(RMAT_GOLDEN):
+        gz = np.load(RMAT_GOLDEN)
+        ids = gz["edge_ids"]
+        ends = np.unique(np.concatenate([u[ids], v[ids]])).astype(np.int32)
+        t0 = time.perf_counter()
+        _, cst = sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=ends)
+        torch.cuda.synchronize()
+        ck = {"sources": int(len(ends)), "s": time.perf_counter() - t0, "walks": cst["walks"],
+              "walk_steps": cst["walk_steps"], "tilde_min": cst["tilde_min"],
+              "tilde_max": cst["tilde_max"]}
+        e = np.abs(out.cpu().numpy()[ids] - gz["sc"])
+        err = float(e.max())
+        checked = int(len(ids))
+        ck["mean_abs_err"] = float(e.mean())
+        print(f"[rmat] error on {checked} sampled edges: max {err:.2e}", file=sys.stderr, flush=True)
+    g.free()
+    line = {
+        "metric": "all-edge SC edges/sec (per-source TGT+, extrapolated from sampled sources)",
+        "value": m / full_s, "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * full_s, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "u64 fixed point + f64", "data": "synthetic",
+        "config": {
+            "workload": f"rmat_s{a.rmat_scale}: R-MAT scale {a.rmat_scale} (a,b,c,d=.57,.19,.19,.05), "
+                        f"edge factor 16, symmetrised, deduplicated, largest component, seed 22: "
+                        f"n={n}, m={m}; TGT+ per source (Eq. 14 switch), eps=1e-2, lambda*-bound "
+                        f"truncation at eps/2",
+            "sample": f"{len(src)} uniform random sources timed in one call ({dt:.2f} s); full call "
+                      f"extrapolated by n/{len(src)}",
+            "sample_sources_per_s": len(src) / dt, "lambda_star": lam,
+            "lambda_converged": st["lambda_converged"], "L_used": st["L_used"],
+            "L_min": st["L_min"], "L_capped": st["L_capped"], "tilde_min": st["tilde_min"],
+            "tilde_max": st["tilde_max"], "walks": st["walks"], "walk_steps": st["walk_steps"],
+            "push_edges": st["push_edges"], "max_abs_err_sampled": err, "checked_edges": checked,
+            "check_call": ck, "generate_s": gen_s, "build_s": build_s, "lambda_s": lam_s,
+        },
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -780,6 +879,9 @@ def main():
         return
     if a.form == "params":
         params_form(a)
+        return
+    if a.form == "rmat":
+        rmat_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc

@@ -176,7 +176,19 @@ def trace_p_power(n, u, v, k):
 
 # ------------------------------------------------------------------ sampled exact ER (large graphs)
 
-def sc_sampled_pcg(n, u, v, edge_ids, tol=1e-12, max_iter=5000, block=256):
+def _laplacian_apply(lap, spmm):
+    """y = L x for a block x: scipy's sparse product, or PyTorch's CPU CSR
+    product (a library matmul that uses every host core) for large graphs."""
+    if spmm == "scipy":
+        return lambda x: lap @ x
+    import torch
+    t = torch.sparse_csr_tensor(torch.from_numpy(lap.indptr.astype(np.int64)),
+                                torch.from_numpy(lap.indices.astype(np.int64)),
+                                torch.from_numpy(lap.data.astype(np.float64)), size=lap.shape)
+    return lambda x: (t @ torch.from_numpy(np.ascontiguousarray(x))).numpy()
+
+
+def sc_sampled_pcg(n, u, v, edge_ids, tol=1e-12, max_iter=5000, block=256, spmm="scipy"):
     """Effective resistance of selected edges by Jacobi-preconditioned block CG.
 
     Solves L x = e_i - e_j (consistent: the right-hand side sums to zero) for
@@ -188,6 +200,7 @@ def sc_sampled_pcg(n, u, v, edge_ids, tol=1e-12, max_iter=5000, block=256):
     a = adjacency_sparse(n, u, v)
     d = np.asarray(a.sum(1)).ravel()
     lap = (sp.diags(d) - a).tocsr()
+    apply = _laplacian_apply(lap, spmm)
     edge_ids = np.asarray(edge_ids, dtype=np.int64)
     out = np.empty(len(edge_ids))
     dinv = 1.0 / d
@@ -204,13 +217,13 @@ def sc_sampled_pcg(n, u, v, edge_ids, tol=1e-12, max_iter=5000, block=256):
         rz = np.einsum("ij,ij->j", r, z)
         bnorm = np.linalg.norm(b, axis=0)
         for _ in range(max_iter):
-            ap = lap @ p
+            ap = apply(p)
             pap = np.einsum("ij,ij->j", p, ap)
             alpha = np.where(pap > 0, rz / np.where(pap > 0, pap, 1.0), 0.0)
             x += alpha * p
             r -= alpha * ap
             if np.all(np.linalg.norm(r, axis=0) <= tol * bnorm):
-                true_r = b - lap @ x
+                true_r = b - apply(x)
                 if np.all(np.linalg.norm(true_r, axis=0) <= 10 * tol * bnorm):
                     break
             z = dinv[:, None] * r

@@ -212,7 +212,6 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   hipStream_t st = static_cast<hipStream_t>(o.stream);
   const bool dev_ptrs = (o.flags & SC_DEVICE_PTRS) != 0;
   if (o.switch_rule != 0 && o.switch_rule != 1) return fail(SC_EINVAL, "switch_rule must be 0 or 1");
-  if (o.gamma > n) return fail(SC_EINVAL, "gamma must not exceed n");
 
   // ---- source list (validated before anything is written)
   const int64_t nsrc = o.sources ? o.nsources : n;

@@ -92,6 +92,7 @@ def main():
     p = argparse.ArgumentParser()
     p.add_argument("--out", default=WEIGHTS, help="path without extension")
     a = p.parse_args()
+    import torch  # noqa: F401  (the device runtime comes up through torch first)
     from paper_2305_16086_amd import sc
     net, rec = train()
     os.makedirs(os.path.dirname(a.out), exist_ok=True)

@@ -114,3 +114,12 @@ def test_batch_golden_matches_pseudoinverse_on_small_graphs():
         sel = gz["graph"] == k
         np.testing.assert_allclose(gz["sc"][sel], ex.sc_pinv(n, u, v)[gz["edge_ids"][sel]],
                                    atol=1e-9, rtol=0)
+
+
+def test_sampled_pcg_torch_products_match_pseudoinverse():
+    import graphgen as gg
+    n, u, v = gg.barabasi_albert(400, 3, 8)
+    ids = np.arange(0, len(u), 5)
+    want = ex.sc_pinv(n, u, v)[ids]
+    np.testing.assert_allclose(ex.sc_sampled_pcg(n, u, v, ids, block=64, spmm="torch"), want,
+                               atol=1e-9, rtol=0)
