@@ -807,10 +807,13 @@ def rmat_form(a):
     sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src[:256])   # buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st = sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src)
+    ot = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE | sc.SC_TIME_KERNELS,
+                               stream=stream.cuda_stream)
+    _, st = sc.sc_all_edges_ex(g, eps, 0, ot, out=out, sources=src)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     full_s = dt * n / len(src)
+    walk_gbs = st["prop_bytes"] / (st["prop_ms"] * 1e-3) / 1e9 if st["prop_ms"] > 0 else 0.0
     print(f"[rmat] {len(src)} sources in {dt:.2f} s -> full call {full_s:.0f} s; walks {st['walks']}, "
           f"push {st['push_edges']}, tilde {st['tilde_min']}..{st['tilde_max']}", file=sys.stderr,
           flush=True)
@@ -851,8 +854,19 @@ def rmat_form(a):
             "tilde_max": st["tilde_max"], "walks": st["walks"], "walk_steps": st["walk_steps"],
             "push_edges": st["push_edges"], "max_abs_err_sampled": err, "checked_edges": checked,
             "check_call": ck, "generate_s": gen_s, "build_s": build_s, "lambda_s": lam_s,
+            "walk_phase_ms": st["prop_ms"], "call_ms": 1e3 * dt,
         },
-        "roofline": None, "cpu_baseline": None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "walk phase of the per-source waves (k_src_scan, k_src_walks, k_src_finish, "
+                      "k_src_clear), timed by events per wave",
+            "achieved": walk_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": walk_gbs / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes": st["prop_bytes"],
+            "alg_bytes_note": "20 B per single-walk step (row bounds 8, neighbour id 4, column entry 8); "
+                              "every access is random, so each moves at least a 64-byte line",
+        },
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

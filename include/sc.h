@@ -249,7 +249,10 @@ int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double*
  * reproducible; precision and block are ignored.  Per-source columns take
  * 24 n bytes per workgroup slot (up to 2048 slots, within a third of the free
  * device memory or SC_SOURCE_SLOT_BYTES).  st: tilde_min / tilde_max,
- * push_edges, walks, walk_steps.
+ * push_edges, walks, walk_steps; with SC_TIME_KERNELS, prop_ms is the time of
+ * the waves' walk phases (events on the stream), prop_launches = prop_timed =
+ * waves and prop_bytes = 20 bytes per single-walk step (row bounds, neighbour
+ * id, column entry).
  */
 
 /* ------------------------------------------------------------------ learned closure

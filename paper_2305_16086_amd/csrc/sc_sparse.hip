@@ -105,7 +105,8 @@ int truncation_rate(sc_graph* g, int L, const sc_options& o, bool allow_compute,
 // no memset (fills are kernels).
 int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, double lam,
                        const SrcBufs& B, int64_t nsrc, const std::vector<int64_t>* hoff,
-                       double* out_dev, int32_t* tau_o, int64_t* nr_o, hipStream_t st) {
+                       double* out_dev, int32_t* tau_o, int64_t* nr_o, hipStream_t st,
+                       const std::vector<hipEvent_t>* walk_ev = nullptr) {
   const int64_t n = g->d.n;
   const int64_t S2 = g->d.nslots;
   int max_L = o.max_L > 0 ? o.max_L : 255;
@@ -177,13 +178,16 @@ int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   wa.k1 = static_cast<unsigned>(o.seed >> 32);
 
   auto at = [&](int64_t k) -> int64_t { return hoff ? (*hoff)[k] : int64_t(g->rowptr_h[k]); };
-  for (int64_t b = 0; b < nsrc; b += B.W) {
+  int64_t wave = 0;
+  for (int64_t b = 0; b < nsrc; b += B.W, ++wave) {
     const int cnt = static_cast<int>(std::min<int64_t>(B.W, nsrc - b));
     a.list_base = b;
     a.pos_base = at(b);
     HIP_TRY(sc::launch_src_head(a, cnt, st));
     wa.P = at(b + cnt) - at(b);
+    if (walk_ev) HIP_TRY(hipEventRecord((*walk_ev)[2 * wave], st));
     HIP_TRY(sc::launch_src_walks(wa, cnt, st));
+    if (walk_ev) HIP_TRY(hipEventRecord((*walk_ev)[2 * wave + 1], st));
   }
   HIP_TRY(sc::launch_combine(g->d, B.gacc, out_dev, st));
   HIP_TRY(sc::launch_trace(g->d, B.tau_slot, B.nr_slot, tau_o, nr_o, st));
@@ -327,8 +331,21 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   }
   sb.clean = false;   // set again once the call has finished
   double* out_dev = dev_ptrs ? out_user : g->out_dev;
+  // SC_TIME_KERNELS: the walk phase of every wave between two timing events
+  std::vector<hipEvent_t> walk_ev;
+  auto destroy_walk_events = [&]() {
+    for (hipEvent_t e : walk_ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  const sc::ScopeExit<decltype(destroy_walk_events)> wev_guard{destroy_walk_events};
+  const int64_t waves = (nsrc + B.W - 1) / B.W;
+  if (o.flags & SC_TIME_KERNELS) {
+    walk_ev.assign(static_cast<size_t>(2 * waves), nullptr);
+    for (auto& e : walk_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  }
   const auto host0 = std::chrono::steady_clock::now();
-  rc = enqueue_per_source(g, eps, L, o, lam, B, nsrc, hp, out_dev, tau_o, nr_o, st);
+  rc = enqueue_per_source(g, eps, L, o, lam, B, nsrc, hp, out_dev, tau_o, nr_o, st,
+                          walk_ev.empty() ? nullptr : &walk_ev);
   if (rc) return rc;
   const double host_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
@@ -356,6 +373,20 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
     s.lambda_converged = conv;
     s.total_ms = ms;
     s.host_ms = host_ms;
+    if (!walk_ev.empty()) {
+      // the walks' algorithmic bytes: per single-walk step the row bounds
+      // (8 B), the neighbour id (4 B) and the column entry (8 B)
+      double wms = 0.0;
+      for (int64_t w = 0; w < waves; ++w) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, walk_ev[2 * w], walk_ev[2 * w + 1]));
+        wms += t;
+      }
+      s.prop_ms = wms;
+      s.prop_launches = waves;
+      s.prop_timed = waves;
+      s.prop_bytes = 20.0 * static_cast<double>(s.walk_steps);
+    }
     *st_user = s;
   }
   return SC_OK;
