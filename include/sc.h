@@ -255,6 +255,30 @@ int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double*
  * id, column entry).
  */
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that forbid allocation): per-source TGT+, as sc_all_edges_ex
+ * with method SC_TGT_PLUS and SC_PER_SOURCE, with every work buffer carved
+ * from a static device array of 128 MiB per GPU (held by each GPU the library
+ * runs on until the process ends) instead of allocated.
+ *   out, and the optional tau_out / tilde_tau_out / nr_out of o: device
+ *   pointers on the handle's device (SC_DEVICE_PTRS is implied); results are
+ *   stream-ordered on o->stream.
+ *   o: method SC_TGT_PLUS (else SC_ENOTIMPL); no source list (SC_EINVAL);
+ *   the automatic truncation needs lambda* already known, from
+ *   o->lambda_star or an earlier sc_lambda_star / run on the handle (SC_EINVAL
+ *   otherwise, since computing it allocates), or a fixed L, or
+ *   SC_TAU_SPECTRAL with a stored spectrum.
+ *   st (may be NULL): as sc_all_edges_ex; asking for it synchronises the stream
+ *   (total_ms is then host time).
+ * Graphs whose buffers do not fit the array (about 20 bytes per half-edge plus
+ * 24 bytes per node and workgroup slot) are refused with SC_EINVAL.  The array
+ * is shared by every call on a GPU and keeps the last call's contents: calls
+ * that overlap on one GPU race.  No memory is allocated; fills are kernels.
+ */
+int sc_all_edges_static(sc_graph* g, double eps, int L, const sc_options* o, double* out,
+                        sc_stats* st);
+
 /* ------------------------------------------------------------------ learned closure
  *
  * Not in the paper: an optional form that stops the traversal after L0 = 8

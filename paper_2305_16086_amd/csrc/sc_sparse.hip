@@ -391,3 +391,140 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   }
   return SC_OK;
 }
+// ====================================================================== no-allocation entry point
+//
+// Every buffer of sc_all_edges_static lives in this array.  In host code its
+// name is only a stand-in for the symbol: the device address, one per GPU,
+// comes from hipGetSymbolAddress on the first call with that device current.
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+constexpr int64_t kStaticPartCapacity = int64_t(1) << 18;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+// Layout of the last run on each device and whether it finished: its columns
+// (Q) were then left all zero, but only a run with the same layout may rely on it
+struct Layout {
+  int64_t n = -1, slots = -1;
+  int W = -1;
+  bool clean = false;
+};
+Layout g_scratch_last[kMaxDevices];
+
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Carve the buffers of a run with W slots from base (null: only measure).
+// Returns the bytes used.
+size_t carve(unsigned char* base, int64_t n, int64_t S2, int W, int64_t P, SrcBufs* B) {
+  size_t off = 0;
+  auto take = [&](auto** p, size_t bytes) {
+    if (base) *p = reinterpret_cast<std::remove_reference_t<decltype(**p)>*>(base + off);
+    off += up256(bytes);
+  };
+  SrcBufs dummy;
+  SrcBufs& b = B ? *B : dummy;
+  take(&b.gacc, sizeof(double) * S2);
+  take(&b.tau_slot, sizeof(int32_t) * S2);
+  take(&b.nr_slot, sizeof(int64_t) * S2);
+  take(&b.tau_row, sizeof(int32_t) * n);
+  take(&b.tilde_row, sizeof(int32_t) * n);
+  take(&b.totals, sizeof(unsigned long long) * kTotals);
+  take(&b.ctl, sizeof(int64_t) * 2);
+  take(&b.slot_ctl, sizeof(int32_t) * 2 * W);
+  take(&b.pos_slot, sizeof(int32_t) * std::max<int64_t>(P, 1));
+  take(&b.pos_w, sizeof(int32_t) * std::max<int64_t>(P, 1));
+  take(&b.nr_pos, sizeof(int64_t) * std::max<int64_t>(P, 1));
+  take(&b.chunk_off, sizeof(int64_t) * (P + 1));
+  take(&b.part, sizeof(double) * kStaticPartCapacity);
+  take(&b.Q, sizeof(uint64_t) * 2 * static_cast<size_t>(W) * n);
+  take(&b.S, sizeof(int32_t) * 2 * static_cast<size_t>(W) * n);
+  b.part_capacity = kStaticPartCapacity;
+  b.W = W;
+  return off;
+}
+
+}  // namespace
+
+extern "C" int sc_all_edges_static(sc_graph* g, double eps, int L, const sc_options* o,
+                                   double* out, sc_stats* st) {
+  if (!g) return fail(SC_EINVAL, "graph is NULL");
+  if (!o) return fail(SC_EINVAL, "options are NULL");
+  if (!out) return fail(SC_EINVAL, "out is NULL");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(SC_EINVAL, "eps must lie in (0, 1)");
+  if (L < 0) return fail(SC_EINVAL, "L must be >= 0");
+  if (o->method != SC_TGT_PLUS) return fail(SC_ENOTIMPL, "sc_all_edges_static runs TGT+ only");
+  if (o->sources) return fail(SC_EINVAL, "sc_all_edges_static takes no source list");
+  if (o->switch_rule != 0 && o->switch_rule != 1) return fail(SC_EINVAL, "switch_rule must be 0 or 1");
+  if (g->device < 0 || g->device >= kMaxDevices) return fail(SC_EINVAL, "device index out of range");
+  const int64_t n = g->d.n, S2 = g->d.nslots;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != g->device) (void)hipSetDevice(g->device);
+  struct Restore {
+    int dev, cur;
+    ~Restore() {
+      if (cur != dev) (void)hipSetDevice(cur);
+    }
+  } restore{g->device, cur};
+  hipStream_t stream = static_cast<hipStream_t>(o->stream);
+
+  // the largest slot count whose buffers fit the array
+  int W = static_cast<int>(std::min<int64_t>(kMaxSlots, n));
+  size_t need = 0;
+  for (;;) {
+    const int64_t P = wave_positions(n, W, nullptr, g->rowptr_h);
+    need = carve(nullptr, n, S2, W, P, nullptr);
+    if (need <= kStaticScratchBytes || W == 1) break;
+    W = std::max(1, W / 2);
+  }
+  if (need > kStaticScratchBytes)
+    return fail(SC_EINVAL, "graph too large for sc_all_edges_static: it needs " +
+                               std::to_string(need) + " bytes of scratch, the static array holds " +
+                               std::to_string(kStaticScratchBytes));
+  double lam = 0.0;
+  int conv = -1;
+  int rc = truncation_rate(g, L, *o, false, stream, &lam, &conv);
+  if (rc) return rc;
+
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  unsigned char*& base = g_scratch_ptr[g->device];
+  if (!base) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    base = static_cast<unsigned char*>(p);
+    g_scratch_last[g->device] = Layout{};
+  }
+  SrcBufs B;
+  carve(base, n, S2, W, wave_positions(n, W, nullptr, g->rowptr_h), &B);
+  // the columns are cleared unless the last run on this GPU finished with the same layout
+  Layout& last = g_scratch_last[g->device];
+  B.Q_clean = last.clean && last.n == n && last.slots == S2 && last.W == W;
+  last = Layout{n, S2, W, false};
+  const auto host0 = std::chrono::steady_clock::now();
+  rc = enqueue_per_source(g, eps, L, *o, lam, B, n, nullptr, out, o->tau_out, o->nr_out, stream);
+  if (rc) return rc;
+  if (o->tilde_tau_out)
+    HIP_TRY(hipMemcpyAsync(o->tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, stream));
+  last.clean = true;   // in stream order, the walks' last pass clears every column it used
+  if (st) {
+    unsigned long long tot[kTotals] = {};
+    HIP_TRY(hipMemcpyAsync(tot, B.totals, sizeof(tot), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    sc_stats s{};
+    fill_stats(tot, &s);
+    s.lambda_star = lam;
+    s.lambda_converged = conv;
+    s.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
+    s.total_ms = s.host_ms;
+    *st = s;
+  }
+  return SC_OK;
+}

@@ -150,6 +150,9 @@ def _load():
     lib.sc_mlp_get.restype = C.c_int
     lib.sc_mlp_set.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.sc_mlp_set.restype = C.c_int
+    lib.sc_all_edges_static.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(ScOptions),
+                                        C.c_void_p, C.POINTER(ScStats)]
+    lib.sc_all_edges_static.restype = C.c_int
     lib.sc_mlp_save.argtypes = [C.c_void_p, C.c_char_p]
     lib.sc_mlp_save.restype = C.c_int
     lib.sc_mlp_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
@@ -202,7 +205,7 @@ EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_gr
             "sc_build_batch", "sc_batch_size", "sc_batch_graph", "sc_free_batch",
             "sc_batch_all_edges", "sc_batch_blocks", "sc_batch_autotune", "sc_batch_load_tuning",
             "sc_compute_spectrum", "sc_set_spectrum", "sc_get_spectrum", "sc_mlp_save",
-            "sc_mlp_load"]
+            "sc_mlp_load", "sc_all_edges_static"]
 
 
 def _check(rc, where):
@@ -380,6 +383,34 @@ def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = No
     st = ScStats()
     rc = _lib.sc_all_edges_ex(g.handle, float(eps), int(L), C.byref(o), _ptr(out), C.byref(st))
     _check(rc, "sc_all_edges_ex")
+    return out, st.as_dict()
+
+
+def sc_all_edges_static(g: Graph, eps: float, L: int, options: ScOptions, out,
+                        tau_out=None, tilde_tau_out=None, nr_out=None):
+    """The allocation-free per-source TGT+ call: ``out`` and the traces are CUDA
+    tensors (the current torch stream unless options.stream is set).  Returns
+    (out, stats dict)."""
+    import torch
+    o = options
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.numel() == g.m):
+        raise ValueError("out must be a CUDA float64 tensor of length m")
+    for arr, name, n_exp, dt in ((tau_out, "tau_out", g.m, torch.int32),
+                                 (tilde_tau_out, "tilde_tau_out", g.n, torch.int32),
+                                 (nr_out, "nr_out", 2 * g.m, torch.int64)):
+        if arr is not None and not (isinstance(arr, torch.Tensor) and arr.is_cuda
+                                    and arr.dtype == dt and arr.numel() == n_exp):
+            raise ValueError(f"{name} must be a CUDA tensor of {n_exp} {dt}")
+    o.flags |= SC_DEVICE_PTRS | SC_PER_SOURCE
+    if not o.stream:
+        o.stream = torch.cuda.current_stream(out.device).cuda_stream
+    o.tau_out = _ptr(tau_out)
+    o.tilde_tau_out = _ptr(tilde_tau_out)
+    o.nr_out = _ptr(nr_out)
+    st = ScStats()
+    rc = _lib.sc_all_edges_static(g.handle, float(eps), int(L), C.byref(o), _ptr(out), C.byref(st))
+    _check(rc, "sc_all_edges_static")
     return out, st.as_dict()
 
 
