@@ -59,7 +59,7 @@ def parse():
     p.add_argument("--cpu-sources", type=int, default=1500,
                    help="sources in the CPU-baseline sample (about 10-15 s of CPU work)")
     p.add_argument("--form", choices=["plain", "batch", "learned", "er", "eps", "caltau",
-                                      "params", "rmat"],
+                                      "params", "rmat", "orkut"],
                    default="plain",
                    help="plain: the BA-100k TGT+ line; batch: 256 mixed graphs in one "
                         "persistent launch against one graph at a time; learned: the "
@@ -172,6 +172,8 @@ def batch_form(a):
         if i % 3 == 2:
             kept, res_ = sc.sc_compute_spectrum(b.graphs[i], 128, 2048, 1e-8)
             spec.append((i, kept, res_))
+            print(f"[batch] spectrum {len(spec)}: grid n={graphs[i][0]}, {kept} pairs "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     spec_s = time.perf_counter() - t0
     print(f"[batch] spectra of {len(spec)} grids: {spec_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -815,6 +817,8 @@ def batch_summary(sc, stream):
 
 
 RMAT_GOLDEN = os.path.join(ROOT, "tests", "golden", "rmat22_seed22_sampled_sc.npz")
+ORKUT_GOLDEN = os.path.join(ROOT, "tests", "golden", "orkut_shaped_sampled_sc.npz")
+ORKUT_N, ORKUT_ATTACH = 3_072_441, 38   # Table 3: n = 3,072,441, m = 117,185,082 (m/n = 38.1)
 
 
 def rmat_form(a):
@@ -826,26 +830,49 @@ def rmat_form(a):
     and the call time is extrapolated by n / sample; the error is checked on the
     512 sampled edges whose exact SC the oracle stored, by a second call over
     their endpoints (both halves of every checked edge computed)."""
+    import graphgen as gg
+    t0 = time.perf_counter()
+    n, u, v = gg.rmat_lcc(a.rmat_scale, 16, seed=22)
+    gen_s = time.perf_counter() - t0
+    name = f"rmat_s{a.rmat_scale}"
+    workload = (f"{name}: R-MAT scale {a.rmat_scale} (a,b,c,d=.57,.19,.19,.05), edge factor 16, "
+                f"symmetrised, deduplicated, largest component, seed 22")
+    sampled_source_form(a, name, workload, (n, u, v), gen_s, 1e-2,
+                        RMAT_GOLDEN if a.rmat_scale == 22 else None)
+
+
+def orkut_form(a):
+    """The Orkut-shaped stand-in (Table 3's node and edge counts): Barabasi-Albert
+    with n = 3,072,441 and 38 edges per new node (m = 116.8 M), seed 1, by
+    per-source TGT+ at eps = 1e-2, timed on sampled sources as the R-MAT form."""
+    import graphgen as gg
+    t0 = time.perf_counter()
+    n, u, v = gg.barabasi_albert(ORKUT_N, ORKUT_ATTACH, SEED, progress=lambda k: print(
+        f"[orkut] generated {k} nodes ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+        flush=True))
+    gen_s = time.perf_counter() - t0
+    workload = (f"orkut_shaped: Barabasi-Albert n={ORKUT_N}, {ORKUT_ATTACH} edges per new node, "
+                f"seed {SEED} (the node and edge counts of the paper's Orkut dataset)")
+    sampled_source_form(a, "orkut_shaped", workload, (n, u, v), gen_s, 1e-2, ORKUT_GOLDEN)
+
+
+def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
     import torch
     from paper_2305_16086_amd import sc
-    import graphgen as gg
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    eps = 1e-2
-    t0 = time.perf_counter()
-    n, u, v = gg.rmat_lcc(a.rmat_scale, 16, seed=22)
+    n, u, v = graph
     m = len(u)
-    gen_s = time.perf_counter() - t0
-    print(f"[rmat] scale {a.rmat_scale}: n={n} m={m} ({gen_s:.0f} s)", file=sys.stderr, flush=True)
+    print(f"[{name}] n={n} m={m} ({gen_s:.0f} s)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     g = sc.sc_build_graph(n, u, v)
     build_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     lam = sc.sc_lambda_star(g)
     lam_s = time.perf_counter() - t0
-    print(f"[rmat] built {build_s:.1f} s, lambda* {lam:.4f} ({lam_s:.1f} s)", file=sys.stderr,
+    print(f"[{name}] built {build_s:.1f} s, lambda* {lam:.4f} ({lam_s:.1f} s)", file=sys.stderr,
           flush=True)
     out = torch.empty(m, dtype=torch.float64, device=dev)
     o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, stream=stream.cuda_stream)
@@ -861,14 +888,14 @@ def rmat_form(a):
     dt = time.perf_counter() - t0
     full_s = dt * n / len(src)
     walk_gbs = st["prop_bytes"] / (st["prop_ms"] * 1e-3) / 1e9 if st["prop_ms"] > 0 else 0.0
-    print(f"[rmat] {len(src)} sources in {dt:.2f} s -> full call {full_s:.0f} s; walks {st['walks']}, "
+    print(f"[{name}] {len(src)} sources in {dt:.2f} s -> full call {full_s:.0f} s; walks {st['walks']}, "
           f"push {st['push_edges']}, tilde {st['tilde_min']}..{st['tilde_max']}", file=sys.stderr,
           flush=True)
     err = None
     checked = 0
     ck = {}
-    if a.rmat_scale == 22 and os.path.exists(RMAT_GOLDEN):
-        gz = np.load(RMAT_GOLDEN)
+    if golden and os.path.exists(golden):
+        gz = np.load(golden)
         ids = gz["edge_ids"]
         ends = np.unique(np.concatenate([u[ids], v[ids]])).astype(np.int32)
         t0 = time.perf_counter()
@@ -881,7 +908,7 @@ def rmat_form(a):
         err = float(e.max())
         checked = int(len(ids))
         ck["mean_abs_err"] = float(e.mean())
-        print(f"[rmat] error on {checked} sampled edges: max {err:.2e}", file=sys.stderr, flush=True)
+        print(f"[{name}] error on {checked} sampled edges: max {err:.2e}", file=sys.stderr, flush=True)
     g.free()
     line = {
         "metric": "all-edge SC edges/sec (per-source TGT+, extrapolated from sampled sources)",
@@ -889,10 +916,8 @@ def rmat_form(a):
         "ms_per_step": 1e3 * full_s, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "u64 fixed point + f64", "data": "synthetic",
         "config": {
-            "workload": f"rmat_s{a.rmat_scale}: R-MAT scale {a.rmat_scale} (a,b,c,d=.57,.19,.19,.05), "
-                        f"edge factor 16, symmetrised, deduplicated, largest component, seed 22: "
-                        f"n={n}, m={m}; TGT+ per source (Eq. 14 switch), eps=1e-2, lambda*-bound "
-                        f"truncation at eps/2",
+            "workload": f"{workload}: n={n}, m={m}; TGT+ per source (Eq. 14 switch), eps={eps}, "
+                        f"lambda*-bound truncation at eps/2",
             "sample": f"{len(src)} uniform random sources timed in one call ({dt:.2f} s); full call "
                       f"extrapolated by n/{len(src)}",
             "sample_sources_per_s": len(src) / dt, "lambda_star": lam,
@@ -943,6 +968,9 @@ def main():
         return
     if a.form == "rmat":
         rmat_form(a)
+        return
+    if a.form == "orkut":
+        orkut_form(a)
         return
     import torch
     from paper_2305_16086_amd import sc

@@ -229,9 +229,10 @@ ER_EDGES_SERIES = [(10_000, m) for m in (200_000, 500_000, 1_000_000, 2_000_000,
 ER_NODES_SERIES = [(n, 1_000_000) for n in (2_000, 5_000, 10_000, 20_000, 50_000)]
 
 
-def barabasi_albert(n: int, m_attach: int, seed: int):
+def barabasi_albert(n: int, m_attach: int, seed: int, progress=None):
     """Preferential attachment: a seed clique on m_attach+1 nodes, then every new
-    node joins m_attach distinct targets drawn with probability proportional to degree."""
+    node joins m_attach distinct targets drawn with probability proportional to degree.
+    ``progress`` (optional) is called with the number of nodes placed every 2^19 nodes."""
     rng = np.random.default_rng(seed)
     k0 = m_attach + 1
     ci, cj = np.triu_indices(k0, 1)
@@ -248,6 +249,8 @@ def barabasi_albert(n: int, m_attach: int, seed: int):
     batch = rng.random(4 * m_attach * (n - k0) + 64)
     bpos = 0
     for new in range(k0, n):
+        if progress is not None and new % (1 << 19) == 0:
+            progress(new)
         chosen = set()
         while len(chosen) < m_attach:
             if bpos >= len(batch):

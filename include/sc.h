@@ -130,7 +130,7 @@ typedef struct sc_stats {
                               queued behind it runs meanwhile)                     */
   int64_t L_capped;        /* edges whose automatic truncation was cut to max_L: the
                               error bound of Theorem 3.2 does not cover them (always 0
-                              with a fixed L)                                        */
+                              with a fixed L; SC_LEARNED: of the fallback truncation) */
   int32_t lambda_converged;/* 1: lambda* from Lanczos runs whose extreme Ritz pairs
                               passed the residual test; 0: a run reached its step limit
                               first (the value is then an estimate only); -1: lambda*

@@ -33,6 +33,8 @@ constexpr int kT = kSrcThreads;           // threads of the per-source workgroup
 constexpr int kTW = kT / 64;              // its waves
 constexpr double kInvUnit = 1.0 / 9223372036854775808.0;   // 2^-63
 constexpr int kWalkGrid = 2048;
+constexpr int kLongRow = 2048;   // N(j) longer than this is scanned by the whole workgroup
+constexpr int kLongList = 256;
 
 __device__ inline int block_scan_excl(int v, int* s_w, int* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -120,6 +122,18 @@ __device__ inline void for_each_edge(const int32_t* __restrict__ list, int cnt,
   }
 }
 
+// x in the sorted neighbour list col[b, e)
+__device__ inline bool adjacent(const int32_t* __restrict__ col, int b, int e, int x) {
+  while (b < e) {
+    const int mid = (b + e) >> 1;
+    const int v = col[mid];
+    if (v == x) return true;
+    if (v < x) b = mid + 1;
+    else e = mid;
+  }
+  return false;
+}
+
 __device__ inline double wave_max_d(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -145,6 +159,8 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
   __shared__ unsigned s_hist[256];
   __shared__ unsigned long long s_bmin[256], s_bmax[256];
   __shared__ int s_cnt;
+  __shared__ int s_long[kLongList];   // halves whose N(j) the whole workgroup scans
+  __shared__ int s_nlong;
   __shared__ uint64_t s_sel[3];   // prefix, threshold, done flag
   __shared__ int s_rank;
 
@@ -291,23 +307,9 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
       minNi = block_reduce(mn, s_rd, [](double x, double y) { return fmin(x, y); });
       // (5) per half (i, j): extremes over N(j), chi (Eq. 17 / Eq. 15), n_r (Eq. 13)
       double part = 0.0;
-      for (int k = rb + wave; k < re; k += kTW) {
-        const int len = a.tau_slot[k] - ell;
-        if (len <= 0) {
-          if (lane == 0) a.nr_slot[k] = 0;
-          continue;
-        }
+      auto count_walks = [&](int k, int len, double jmx, double jmn) {
         double chiQ;
         if (a.gamma > 0) {
-          const int j = a.col[k];
-          double jmx = -DBL_MAX, jmn = DBL_MAX;
-          for (int q = a.rowptr[j] + lane; q < a.rowptr[j + 1]; q += 64) {
-            const double v = static_cast<double>(Qc[a.col[q]]);
-            jmx = fmax(jmx, v);
-            jmn = fmin(jmn, v);
-          }
-          jmx = wave_max_d(jmx);
-          jmn = wave_min_d(jmn);
           const double lb_i = minNi + (len - 1) * minV;
           const double ub_i = maxNi * 0.5 + maxV * 0.5 + (len - 1) * rhoQ * 0.5;
           const double lb_j = jmn + (len - 1) * minV;
@@ -321,10 +323,85 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
         double r = ceil(a.coef * chi * chi);
         if (!(r >= 1.0)) r = 1.0;
         const long long nr = r > static_cast<double>(a.nr_cap) ? a.nr_cap : static_cast<long long>(r);
-        if (lane == 0) {
-          a.nr_slot[k] = nr;
-          part += a.rule == 0 ? static_cast<double>(nr) : 2.0 * len * static_cast<double>(nr);
+        a.nr_slot[k] = nr;
+        part += a.rule == 0 ? static_cast<double>(nr) : 2.0 * len * static_cast<double>(nr);
+      };
+      if (tid == 0) s_nlong = 0;
+      __syncthreads();
+      for (int k = rb + wave; k < re; k += kTW) {
+        const int len = a.tau_slot[k] - ell;
+        if (len <= 0) {
+          if (lane == 0) a.nr_slot[k] = 0;
+          continue;
         }
+        if (a.gamma > 0) {
+          const int j = a.col[k];
+          const int jb = a.rowptr[j], je = a.rowptr[j + 1];
+          double jmx, jmn;
+          if (je - jb > kLongRow && static_cast<int64_t>(cnt) * 4 >= je - jb) {
+            // a hub's list: left to the whole workgroup below (or scanned here
+            // when the list of such halves is full)
+            int slot = -1;
+            if (lane == 0) slot = atomicAdd(&s_nlong, 1);
+            slot = __shfl(slot, 0, 64);
+            if (slot < kLongList) {
+              if (lane == 0) s_long[slot] = k;
+              continue;
+            }
+          }
+          if (static_cast<int64_t>(cnt) * 4 < je - jb) {
+            // a short support against a long N(j) (a hub): visit the support and
+            // test adjacency to j instead; q is zero off the support, so the
+            // extremes over N(j) are those of the support nodes in N(j), with
+            // the minimum 0 unless they fill N(j)
+            double mx = 0.0, mn = DBL_MAX;
+            int hits = 0;
+            for (int e = lane; e < cnt; e += 64) {
+              const int y = Sc[e];
+              const int yb = a.rowptr[y], ye = a.rowptr[y + 1];
+              const bool in_j = ye - yb < je - jb ? adjacent(a.col, yb, ye, j)
+                                                  : adjacent(a.col, jb, je, y);
+              if (in_j) {
+                const double v = static_cast<double>(Qc[y]);
+                mx = fmax(mx, v);
+                mn = fmin(mn, v);
+                ++hits;
+              }
+            }
+            jmx = wave_max_d(mx);
+            mn = wave_min_d(mn);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) hits += __shfl_xor(hits, off, 64);
+            jmn = hits < je - jb ? 0.0 : mn;
+          } else {
+            double mx = -DBL_MAX, mn = DBL_MAX;
+            for (int q = jb + lane; q < je; q += 64) {
+              const double v = static_cast<double>(Qc[a.col[q]]);
+              mx = fmax(mx, v);
+              mn = fmin(mn, v);
+            }
+            jmx = wave_max_d(mx);
+            jmn = wave_min_d(mn);
+          }
+          if (lane == 0) count_walks(k, len, jmx, jmn);
+        } else if (lane == 0) {
+          count_walks(k, len, 0.0, 0.0);
+        }
+      }
+      __syncthreads();
+      const int nlong = s_nlong < kLongList ? s_nlong : kLongList;
+      for (int t = 0; t < nlong; ++t) {   // hubs' lists, all threads at once
+        const int k = s_long[t];
+        const int j = a.col[k];
+        double mx = -DBL_MAX, mn = DBL_MAX;
+        for (int q = a.rowptr[j] + tid; q < a.rowptr[j + 1]; q += kT) {
+          const double v = static_cast<double>(Qc[a.col[q]]);
+          mx = fmax(mx, v);
+          mn = fmin(mn, v);
+        }
+        mx = block_reduce(mx, s_rd, [](double x, double y) { return fmax(x, y); });
+        mn = block_reduce(mn, s_rd, [](double x, double y) { return fmin(x, y); });
+        if (tid == 0) count_walks(k, a.tau_slot[k] - ell, mx, mn);
       }
       rhs = block_reduce(part, s_rd, AddD{});
     }
@@ -600,6 +677,23 @@ __global__ __launch_bounds__(256) void k_tau_range(int n, const int32_t* __restr
   }
 }
 
+// vol[x] = sum over the neighbours j of x of d_j (one wave per node)
+__global__ __launch_bounds__(256) void k_nbr_volume(int n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    int64_t* __restrict__ vol) {
+  const int x = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (x >= n) return;
+  int64_t v = 0;
+  for (int k = rowptr[x] + lane; k < rowptr[x + 1]; k += 64) {
+    const int j = col[k];
+    v += rowptr[j + 1] - rowptr[j];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) vol[x] = v;
+}
+
 inline unsigned fill_grid(int64_t count) {
   const int64_t g = (count + 255) / 256;
   return static_cast<unsigned>(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -616,6 +710,11 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   k_fill_u32<<<fill_grid(count), 256, 0, st>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_nbr_volume(const DeviceGraph& g, int64_t* vol, hipStream_t st) {
+  k_nbr_volume<<<static_cast<unsigned>((g.n + 3) / 4), 256, 0, st>>>(g.n, g.rowptr, g.col, vol);
   return hipGetLastError();
 }
 

@@ -148,6 +148,7 @@ struct sc_graph {
     size_t list_cap = 0;
     int64_t* hoff = nullptr;
     size_t hoff_cap = 0;
+    std::vector<int64_t> nbr_vol_h;   // per node: sum of its neighbours' degrees (wave order)
   } src;
   double* out_dev = nullptr;
   int32_t* tau_out_dev = nullptr;

@@ -330,6 +330,8 @@ hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st);
 // plain fills (kernels, so that a captured sequence holds no memset nodes)
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t st);
+// vol[x] = sum of the degrees of x's neighbours (the first push of source x)
+hipError_t launch_nbr_volume(const DeviceGraph& g, int64_t* vol, hipStream_t st);
 // mm[0] = min(mm[0], min tau_row), mm[1] = max(mm[1], max tau_row)
 hipError_t launch_tau_range(int n, const int32_t* tau_row, unsigned long long* mm, hipStream_t st);
 // scan, walks, finish and the clearing of the wave's columns

@@ -424,27 +424,41 @@ int learned_t(sc_graph* g, double eps, const sc_options& o, double* out_user, sc
   if (rc) return rc;
   rc = sc::ensure_closure_buffers(g, sizeof(T));
   if (rc) return rc;
-  hipEvent_t t0, t1;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  auto destroy_events = [&]() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+  const sc::ScopeExit<decltype(destroy_events)> ev_guard{destroy_events};   // every return path
   HIP_TRY(hipEventCreate(&t0));
   HIP_TRY(hipEventCreate(&t1));
   HIP_TRY(hipEventRecord(t0, st));
   double lam = o.lambda_star;
+  int converged = -1;
   if (!(lam > 0.0)) {
     rc = sc::graph_lambda_star(g, st, &lam);
     if (rc) return rc;
+    converged = g->lambda_converged;
   }
   int max_L = o.max_L > 0 ? o.max_L : 255;
   if (max_L % 2 == 0) --max_L;
-  // fallback truncation: Theorem 3.2 at eps
-  HIP_TRY(sc::launch_tau(g->d, 0, eps, lam, max_L, g->tau_slot, g->tau_row, st));
+  // fallback truncation: Theorem 3.2 at eps (its cut edges counted in work[2])
+  unsigned long long* capped = g->work + 2;
+  HIP_TRY(hipMemsetAsync(capped, 0, sizeof(unsigned long long), st));
+  HIP_TRY(sc::launch_tau(g->d, 0, eps, lam, max_L, g->tau_slot, g->tau_row, st, capped));
   std::vector<int32_t> tau_row(n);
+  unsigned long long capped_h = 0;
   HIP_TRY(hipMemcpyAsync(tau_row.data(), g->tau_row, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&capped_h, capped, sizeof(capped_h), hipMemcpyDeviceToHost, st));
   HIP_TRY(sc::launch_gacc_init(g->d, g->tau_slot, 1, g->gacc, st));
 
   sc::Runner<T> R{g, B, st, (o.flags & SC_TIME_KERNELS) != 0};
   R.stats.block = B;
   R.stats.tilde_tau = -1;
+  R.stats.tilde_min = -1;
+  R.stats.tilde_max = -1;
   R.stats.lambda_star = lam;
+  R.stats.lambda_converged = converged;
   double* s0 = g->cl_s0;
   double* uK = s0 + m;
   double* lo = s0 + 2 * m;
@@ -487,9 +501,8 @@ int learned_t(sc_graph* g, double eps, const sc_options& o, double* out_user, sc
   HIP_TRY(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   R.stats.total_ms = ms;
+  R.stats.L_capped = static_cast<int64_t>(capped_h / 2);   // of the fallback truncation
   R.stats.L_used = Lmax;
   R.stats.L_min = sc::kRecSteps;
   R.stats.fallback_edges = static_cast<int64_t>(cnt[0]);

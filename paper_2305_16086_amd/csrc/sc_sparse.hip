@@ -217,24 +217,49 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   const bool dev_ptrs = (o.flags & SC_DEVICE_PTRS) != 0;
   if (o.switch_rule != 0 && o.switch_rule != 1) return fail(SC_EINVAL, "switch_rule must be 0 or 1");
 
-  // ---- source list (validated before anything is written)
+  // ---- source list (validated before anything is written), ordered by the
+  // volume of the source's neighbourhood, largest first: a wave lasts as long as
+  // its slowest source, so sources of similar cost share waves
   const int64_t nsrc = o.sources ? o.nsources : n;
   if (o.sources && (o.nsources <= 0 || o.nsources > n))
     return fail(SC_EINVAL, "nsources must lie in [1, n]");
-  std::vector<int64_t> hoff;
+  std::vector<int32_t> order(nsrc);
   if (o.sources) {
     std::vector<unsigned char> seen(n, 0);
-    hoff.resize(nsrc + 1);
-    hoff[0] = 0;
     for (int64_t k = 0; k < nsrc; ++k) {
       const int32_t s = o.sources[k];
       if (s < 0 || s >= n) return fail(SC_EINVAL, "source id out of range");
       if (seen[s]) return fail(SC_EINVAL, "source listed twice");
       seen[s] = 1;
-      hoff[k + 1] = hoff[k] + (g->rowptr_h[s + 1] - g->rowptr_h[s]);
+      order[k] = s;
+    }
+  } else {
+    for (int64_t k = 0; k < nsrc; ++k) order[k] = static_cast<int32_t>(k);
+  }
+  auto& sb0 = g->src;
+  if (sb0.nbr_vol_h.empty()) {
+    int64_t* vol = nullptr;
+    HIP_TRY(dev_alloc(&vol, n));
+    const hipError_t e1 = sc::launch_nbr_volume(g->d, vol, st);
+    sb0.nbr_vol_h.resize(n);
+    const hipError_t e2 = e1 == hipSuccess ? hipMemcpyAsync(sb0.nbr_vol_h.data(), vol, n * sizeof(int64_t),
+                                                            hipMemcpyDeviceToHost, st)
+                                           : e1;
+    const hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
+    dev_free(vol);
+    if (e3 != hipSuccess) {
+      sb0.nbr_vol_h.clear();
+      return fail(SC_EHIP, std::string("neighbourhood volumes: ") + hipGetErrorString(e3));
     }
   }
-  const std::vector<int64_t>* hp = o.sources ? &hoff : nullptr;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return sb0.nbr_vol_h[x] > sb0.nbr_vol_h[y];
+  });
+  std::vector<int64_t> hoff(nsrc + 1);
+  hoff[0] = 0;
+  for (int64_t k = 0; k < nsrc; ++k)
+    hoff[k + 1] = hoff[k] + (g->rowptr_h[order[k] + 1] - g->rowptr_h[order[k]]);
+  const std::vector<int64_t>* hp = &hoff;
 
   // ---- slots: two n-word columns and two n-entry lists each
   const size_t per_slot = static_cast<size_t>(n) * (2 * sizeof(uint64_t) + 2 * sizeof(int32_t));
@@ -276,10 +301,8 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   HIP_TRY(grow(&sb.part, &sb.part_cap, static_cast<size_t>(kPartCapacity)));
   HIP_TRY(grow(&sb.ctl, &sb.ctl2_cap, size_t(2)));
   HIP_TRY(grow(&sb.totals, &sb.tot_cap, size_t(kTotals)));
-  if (o.sources) {
-    HIP_TRY(grow(&sb.list, &sb.list_cap, static_cast<size_t>(nsrc)));
-    HIP_TRY(grow(&sb.hoff, &sb.hoff_cap, static_cast<size_t>(nsrc) + 1));
-  }
+  HIP_TRY(grow(&sb.list, &sb.list_cap, static_cast<size_t>(nsrc)));
+  HIP_TRY(grow(&sb.hoff, &sb.hoff_cap, static_cast<size_t>(nsrc) + 1));
   int32_t* tau_o = nullptr;
   int64_t* nr_o = nullptr;
   if (o.tau_out) {
@@ -308,8 +331,8 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
     B.part_capacity = std::max<int64_t>(1, std::min<int64_t>(kPartCapacity, std::atoll(c)));
   B.ctl = sb.ctl;
   B.totals = sb.totals;
-  B.list = o.sources ? sb.list : nullptr;
-  B.hoff = o.sources ? sb.hoff : nullptr;
+  B.list = sb.list;
+  B.hoff = sb.hoff;
   B.Q_clean = sb.clean;
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -325,10 +348,8 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   int conv = -1;
   int rc = truncation_rate(g, L, o, true, st, &lam, &conv);
   if (rc) return rc;
-  if (o.sources) {
-    HIP_TRY(hipMemcpyAsync(B.list, o.sources, nsrc * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(B.hoff, hoff.data(), (nsrc + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  }
+  HIP_TRY(hipMemcpyAsync(B.list, order.data(), nsrc * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.hoff, hoff.data(), (nsrc + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   sb.clean = false;   // set again once the call has finished
   double* out_dev = dev_ptrs ? out_user : g->out_dev;
   // SC_TIME_KERNELS: the walk phase of every wave between two timing events
