@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
           const int j = a.col[k];
           const int jb = a.rowptr[j], je = a.rowptr[j + 1];
           double jmx, jmn;
-          if (je - jb > kLongRow && static_cast<int64_t>(cnt) * 4 >= je - jb) {
+          if (je - jb > kLongRow && static_cast<int64_t>(cnt) * 16 >= je - jb) {
             // a hub's list: left to the whole workgroup below (or scanned here
             // when the list of such halves is full)
             int slot = -1;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
               continue;
             }
           }
-          if (static_cast<int64_t>(cnt) * 4 < je - jb) {
+          if (static_cast<int64_t>(cnt) * 16 < je - jb) {
             // a short support against a long N(j) (a hub): visit the support and
             // test adjacency to j instead; q is zero off the support, so the
             // extremes over N(j) are those of the support nodes in N(j), with
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(256) void k_src_walks(SrcWalkArgs a) {
   auto slot_q = [&](int w) {
     return a.Q + (2 * static_cast<size_t>(w) + static_cast<size_t>(a.slot_ctl[2 * w + 1])) * n;
   };
-  if (a.ctl[1] == 0) {
+  if (a.cend < 0 && a.ctl[1] == 0) {
     // the chunks do not fit the partial-sum buffer: one wave per half-edge
     for (long long p = wv; p < a.P; p += nwaves) {
       const long long nr = a.nr_pos[p];
@@ -585,10 +585,12 @@ __global__ __launch_bounds__(256) void k_src_walks(SrcWalkArgs a) {
     }
     return;
   }
-  const long long total = a.ctl[0];
-  const long long per = (total + nwaves - 1) / nwaves;
-  const long long c0 = wv * per;
-  const long long c1 = min(total, c0 + per);
+  // chunks [cb, ce): a batch given by the host, or all of them
+  const long long cb = a.cend < 0 ? 0 : a.cbeg;
+  const long long ce = a.cend < 0 ? a.ctl[0] : a.cend;
+  const long long per = (ce - cb + nwaves - 1) / nwaves;
+  const long long c0 = cb + wv * per;
+  const long long c1 = min(ce, c0 + per);
   if (c0 >= c1) return;
   long long lo = 0, hi = a.P;   // chunk_off[lo] <= c0 < chunk_off[hi]
   while (hi - lo > 1) {
@@ -613,18 +615,23 @@ __global__ __launch_bounds__(256) void k_src_walks(SrcWalkArgs a) {
       x = walk_pair(i, j, r, len, a.k0, a.k1, a.rowptr, a.col, slot_q(a.pos_w[p]));
     }
     x = wave_sum_d(x);
-    if (lane == 0) a.part[c] = x;
+    if (lane == 0) a.part[c - cb] = x;
   }
 }
 
 // gacc[k] += (chunk sums of half p in chunk order) / n_r
 __global__ __launch_bounds__(256) void k_src_finish(SrcWalkArgs a) {
   const long long p = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-  if (p >= a.P || a.ctl[1] == 0) return;
+  if (p >= a.P || (a.cend < 0 && a.ctl[1] == 0)) return;
   const long long nr = a.nr_pos[p];
   if (nr <= 0) return;
+  // the half's chunks inside this batch, in chunk order
+  const long long cb = a.cend < 0 ? 0 : a.cbeg;
+  const long long lo = max(a.chunk_off[p], cb);
+  const long long hi = a.cend < 0 ? a.chunk_off[p + 1] : min(a.chunk_off[p + 1], a.cend);
+  if (lo >= hi) return;
   double s = 0.0;
-  for (long long c = a.chunk_off[p]; c < a.chunk_off[p + 1]; ++c) s += a.part[c];
+  for (long long c = lo; c < hi; ++c) s += a.part[c - cb];
   a.gacc[a.pos_slot[p]] += s / static_cast<double>(nr);
 }
 
@@ -729,19 +736,31 @@ hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st) {
+hipError_t launch_src_scan(const SrcWalkArgs& a, hipStream_t st) {
   if (a.P <= 0) return hipSuccess;
   k_src_scan<<<1, 256, 0, st>>>(a.P, a.nr_pos, a.chunk_off, a.capacity, a.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_src_walk_batch(const SrcWalkArgs& a, hipStream_t st) {
+  if (a.P <= 0) return hipSuccess;
+  k_src_walks<<<kWalkGrid, 256, 0, st>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_src_walks<<<kWalkGrid, 256, 0, st>>>(a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   k_src_finish<<<static_cast<unsigned>((a.P + 255) / 256), 256, 0, st>>>(a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_src_clear(const SrcWalkArgs& a, int nslots_used, hipStream_t st) {
   k_src_clear<<<nslots_used, 256, 0, st>>>(a.n, nslots_used, a.Qw, a.S, a.slot_ctl);
   return hipGetLastError();
+}
+
+hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st) {
+  hipError_t e = launch_src_scan(a, st);
+  if (e == hipSuccess) e = launch_src_walk_batch(a, st);
+  if (e == hipSuccess) e = launch_src_clear(a, nslots_used, st);
+  return e;
 }
 
 }  // namespace sc

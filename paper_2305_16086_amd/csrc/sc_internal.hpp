@@ -324,6 +324,10 @@ struct SrcWalkArgs {
   int64_t capacity = 0;
   double* gacc = nullptr;
   unsigned k0 = 0, k1 = 0;         // Philox key
+  // a batch of chunks [cbeg, cend) set by the host (part holds the batch from
+  // index 0); cend < 0: all chunks at once, or one wave per half when they do
+  // not fit the buffer (ctl[1] == 0)
+  int64_t cbeg = 0, cend = -1;
 };
 
 hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st);
@@ -336,6 +340,11 @@ hipError_t launch_nbr_volume(const DeviceGraph& g, int64_t* vol, hipStream_t st)
 hipError_t launch_tau_range(int n, const int32_t* tau_row, unsigned long long* mm, hipStream_t st);
 // scan, walks, finish and the clearing of the wave's columns
 hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st);
+// the same in parts: the chunk scan (ctl[0] = chunks), one batch of walks with
+// its finish pass, the clearing of the columns
+hipError_t launch_src_scan(const SrcWalkArgs& a, hipStream_t st);
+hipError_t launch_src_walk_batch(const SrcWalkArgs& a, hipStream_t st);
+hipError_t launch_src_clear(const SrcWalkArgs& a, int nslots_used, hipStream_t st);
 
 // --------------------------------------------------------------- learned closure
 constexpr int kMlpParams = 5313;

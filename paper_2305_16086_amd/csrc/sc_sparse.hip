@@ -106,7 +106,8 @@ int truncation_rate(sc_graph* g, int L, const sc_options& o, bool allow_compute,
 int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, double lam,
                        const SrcBufs& B, int64_t nsrc, const std::vector<int64_t>* hoff,
                        double* out_dev, int32_t* tau_o, int64_t* nr_o, hipStream_t st,
-                       const std::vector<hipEvent_t>* walk_ev = nullptr) {
+                       const std::vector<hipEvent_t>* walk_ev = nullptr,
+                       bool batch_walks = false) {
   const int64_t n = g->d.n;
   const int64_t S2 = g->d.nslots;
   int max_L = o.max_L > 0 ? o.max_L : 255;
@@ -186,7 +187,24 @@ int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
     HIP_TRY(sc::launch_src_head(a, cnt, st));
     wa.P = at(b + cnt) - at(b);
     if (walk_ev) HIP_TRY(hipEventRecord((*walk_ev)[2 * wave], st));
-    HIP_TRY(sc::launch_src_walks(wa, cnt, st));
+    if (batch_walks && wa.P > 0) {
+      // the host reads the wave's chunk count and walks them in batches of the
+      // buffer's capacity, so no half is left to a single wave however many
+      // walks it has
+      HIP_TRY(sc::launch_src_scan(wa, st));
+      int64_t total = 0;
+      HIP_TRY(hipMemcpyAsync(&total, B.ctl, sizeof(total), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int64_t c = 0; c < total; c += wa.capacity) {
+        sc::SrcWalkArgs wb = wa;
+        wb.cbeg = c;
+        wb.cend = std::min(total, c + wa.capacity);
+        HIP_TRY(sc::launch_src_walk_batch(wb, st));
+      }
+      HIP_TRY(sc::launch_src_clear(wa, cnt, st));
+    } else {
+      HIP_TRY(sc::launch_src_walks(wa, cnt, st));
+    }
     if (walk_ev) HIP_TRY(hipEventRecord((*walk_ev)[2 * wave + 1], st));
   }
   HIP_TRY(sc::launch_combine(g->d, B.gacc, out_dev, st));
@@ -366,7 +384,7 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   }
   const auto host0 = std::chrono::steady_clock::now();
   rc = enqueue_per_source(g, eps, L, o, lam, B, nsrc, hp, out_dev, tau_o, nr_o, st,
-                          walk_ev.empty() ? nullptr : &walk_ev);
+                          walk_ev.empty() ? nullptr : &walk_ev, true);
   if (rc) return rc;
   const double host_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
