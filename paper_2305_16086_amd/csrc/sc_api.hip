@@ -881,14 +881,20 @@ int ensure_buffers(sc_graph* g, int B, size_t tsize) {
   const int64_t n = g->d.n;
   const int64_t S = static_cast<int64_t>(g->rowptr_h[n]);
   const size_t yb = static_cast<size_t>(n) * B * tsize;
-  if (yb > g->ybytes) {
+  // blocks per pipeline group: as many as the budget allows (at least one)
+  int group = sc::kMaxGroupBlocks;
+  while (group > 1 && 2 * sc::kPipeGroups * group * yb > sc::kPipeBudgetBytes) group /= 2;
+  const int pairs = sc::kPipeGroups * group;
+  if (yb > g->ybytes || pairs != g->ypairs) {
     for (auto& y : g->Y) {
       if (y) (void)sc::tracked_free(y);
       y = nullptr;
     }
     g->ybytes = 0;
-    for (auto& y : g->Y) HIP_TRY(sc::tracked_malloc(&y, yb));
+    g->ypairs = 0;
+    for (int i = 0; i < 2 * pairs; ++i) HIP_TRY(sc::tracked_malloc(&g->Y[i], yb));
     g->ybytes = yb;
+    g->ypairs = pairs;
   }
   if (!g->nz) {
     HIP_TRY(dev_alloc(&g->nz, n));
@@ -1137,21 +1143,71 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   HIP_TRY(hipMemsetAsync(work, 0, 2 * sizeof(unsigned long long), st));
   // Block pipeline: the traversal of block b runs on the caller's stream, its
   // tail (last accumulation, candidate summary, walk counts, walks) on the
-  // tail stream, overlapping the traversals of the next blocks.  Blocks cycle
-  // through kPipeDepth Y pairs; a pair is reused only after the tail of the
-  // block kPipeDepth back has finished.  Blocks touch disjoint slots of gacc
-  // and nr_slot.
+  // tail stream, overlapping the traversals of the next blocks.  The streams
+  // meet once per group of G blocks: the tails of a group wait for the whole
+  // group's traversal, and the traversal of group q waits for the tails of
+  // group q - kPipeGroups, whose Y pairs it reuses (block i of the launched
+  // sequence takes pair i mod (kPipeGroups G)).  Blocks touch disjoint slots
+  // of gacc and nr_slot.
   rc = sc::ensure_pipeline(g);
   if (rc) return rc;
   hipStream_t sb = g->tail_stream;
   HIP_TRY(hipEventRecord(g->pipe_ev[0], st));
   HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[0], 0));
   const auto host0 = std::chrono::steady_clock::now();
-  constexpr int D = sc::kPipeDepth;
-  bool tail_recorded[D] = {};
+  constexpr int Q = sc::kPipeGroups;
+  const int D = g->ypairs;
+  const int G = D / Q;
+  bool tail_recorded[Q] = {};
   // the last pass of a block's walks rides on the next candidate summary's
   // first launch (same stream, before the next walks reuse the chunk buffers)
   sc::FinishJob fin;
+  // a traversed block whose tail is not yet enqueued
+  struct TailJob {
+    int s0, kbeg, kend, tmax, pair, cur;
+    sc::AccJob acc;
+  };
+  std::vector<TailJob> group_jobs;
+  group_jobs.reserve(G);
+  auto enqueue_tails = [&](int qset) -> int {
+    HIP_TRY(hipEventRecord(g->pipe_ev[1 + qset], st));
+    HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[1 + qset], 0));
+    R.st = sb;
+    for (const TailJob& tj : group_jobs) {
+      R.po = 2 * tj.pair;
+      R.cur = tj.cur;
+      R.pending_acc = tj.acc;
+      // the last step's accumulation rides on the candidate summary's first
+      // launch when there is one (same state, same stream)
+      const bool fuse_acc = plus && tj.tmax > tilde && tilde >= 2;
+      if (!fuse_acc) {
+        const int rc1 = R.flush_acc();
+        if (rc1) return rc1;
+      }
+      if (plus && tj.tmax > tilde) {
+        if (tilde < 2) {
+          const int rc1 = R.init_low(tj.s0, tilde);
+          if (rc1) return rc1;
+        }
+        HIP_TRY(sc::launch_colstats<T>(g->d, tj.s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch,
+                                       sb, fuse_acc ? &R.pending_acc : nullptr, &fin));
+        R.pending_acc = sc::AccJob{};
+        fin = sc::FinishJob{};
+        HIP_TRY(sc::launch_walk_counts<T>(g->d, tj.kbeg, tj.kend, tj.s0, B, tilde, gamma, coef,
+                                          nr_cap, R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot,
+                                          sb));
+        HIP_TRY(sc::launch_walks<T>(g->d, tj.kbeg, tj.kend, tj.s0, B, tilde, o.seed,
+                                    R.Yb(R.cur), g->tau_slot, g->nr_slot, g->gacc, g->walk, sb,
+                                    &fin));
+      }
+    }
+    group_jobs.clear();
+    HIP_TRY(hipEventRecord(g->pipe_ev[1 + Q + qset], sb));
+    tail_recorded[qset] = true;
+    R.st = st;
+    return SC_OK;
+  };
+  int launched = 0;   // blocks traversed so far
   for (int b = 0; b < nblocks; ++b) {
     int s0, kbeg, kend, tmax;
     block_range(b, &s0, &kbeg, &kend, &tmax);
@@ -1159,39 +1215,25 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
     // a block whose edges all stop at tau <= 1 has only the l = 0, 1 terms,
     // which the accumulator initialisation already holds: no launch, no events
     if (lend < 2 && !(plus && tmax > tilde)) continue;
-    const int pair = b % D;
-    if (tail_recorded[pair]) HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[1 + D + pair], 0));
+    const int pair = launched % D;
+    const int qset = (launched / G) % Q;
+    if (launched % G == 0 && tail_recorded[qset])
+      HIP_TRY(hipStreamWaitEvent(st, g->pipe_ev[1 + Q + qset], 0));
     R.st = st;
     R.po = 2 * pair;
     rc = R.traverse(s0, kbeg, kend, lend, true, g->gacc, b + 1 < nblocks ? s0 + B : -1);
     if (rc) return rc;
-    HIP_TRY(hipEventRecord(g->pipe_ev[1 + pair], st));
-    HIP_TRY(hipStreamWaitEvent(sb, g->pipe_ev[1 + pair], 0));
-    R.st = sb;
-    // the last step's accumulation rides on the candidate summary's first
-    // launch when there is one (same state, same stream)
-    const bool fuse_acc = plus && tmax > tilde && tilde >= 2;
-    if (!fuse_acc) {
-      rc = R.flush_acc();
+    group_jobs.push_back(TailJob{s0, kbeg, kend, tmax, pair, R.cur, R.pending_acc});
+    R.pending_acc = sc::AccJob{};
+    ++launched;
+    if (launched % G == 0) {
+      rc = enqueue_tails(qset);
       if (rc) return rc;
     }
-    if (plus && tmax > tilde) {
-      if (tilde < 2) {
-        rc = R.init_low(s0, tilde);
-        if (rc) return rc;
-      }
-      HIP_TRY(sc::launch_colstats<T>(g->d, s0, B, gamma, R.Yb(R.cur), g->cs, g->colscratch, sb,
-                                     fuse_acc ? &R.pending_acc : nullptr, &fin));
-      R.pending_acc = sc::AccJob{};
-      fin = sc::FinishJob{};
-      HIP_TRY(sc::launch_walk_counts<T>(g->d, kbeg, kend, s0, B, tilde, gamma, coef, nr_cap,
-                                        R.Yb(R.cur), g->cs, g->tau_slot, g->nr_slot, sb));
-      HIP_TRY(sc::launch_walks<T>(g->d, kbeg, kend, s0, B, tilde, o.seed, R.Yb(R.cur),
-                                  g->tau_slot, g->nr_slot, g->gacc, g->walk, sb, &fin));
-    }
-    HIP_TRY(hipEventRecord(g->pipe_ev[1 + D + pair], sb));
-    tail_recorded[pair] = true;
-    R.st = st;
+  }
+  if (!group_jobs.empty()) {
+    rc = enqueue_tails(((launched - 1) / G) % Q);
+    if (rc) return rc;
   }
   R.stats.host_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();

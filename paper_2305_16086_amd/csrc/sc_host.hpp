@@ -42,9 +42,15 @@ void dev_free(P*& p) {
   p = nullptr;
 }
 
-// Source blocks in flight in the per-graph pipeline: the traversal of block b
-// reuses the Y pair of block b - kPipeDepth once that block's tail is done.
-constexpr int kPipeDepth = 3;
+// The per-graph block pipeline synchronises its two streams once per group of
+// blocks; groups cycle through kPipeGroups sets of Y pairs, so the traversal of
+// group q reuses the pairs of group q - kPipeGroups once that group's tails are
+// done.  A group holds up to kMaxGroupBlocks blocks (fewer when the Y pairs of
+// the larger pipeline would not fit kPipeBudgetBytes).
+constexpr int kPipeGroups = 3;
+constexpr int kMaxGroupBlocks = 4;
+constexpr int kMaxPipe = kPipeGroups * kMaxGroupBlocks;   // Y pairs at most
+constexpr size_t kPipeBudgetBytes = size_t(2) << 30;
 
 // runs f when the scope ends (releases buffers on every return path)
 template <typename F>
@@ -80,12 +86,13 @@ struct sc_graph {
   std::vector<double> spec_lam_h;
 
   // work buffers, grown on demand
-  void* Y[2 * sc::kPipeDepth] = {};        // one ping-pong pair per block in flight
+  void* Y[2 * sc::kMaxPipe] = {};          // one ping-pong pair per block in flight
   size_t ybytes = 0;
+  int ypairs = 0;                          // pairs allocated (kPipeGroups x group size)
   hipStream_t tail_stream = nullptr;   // per-block tails overlap the next traversal
-  // [0] stream joins, [1 + p] traversal of the block in pair p done,
-  // [1 + kPipeDepth + p] its tail done
-  hipEvent_t pipe_ev[1 + 2 * sc::kPipeDepth] = {};
+  // [0] stream joins, [1 + q] traversal of the group in set q done,
+  // [1 + kPipeGroups + q] its tails done
+  hipEvent_t pipe_ev[1 + 2 * sc::kPipeGroups] = {};
   void* partials = nullptr;
   size_t pbytes = 0;
   unsigned long long* mask = nullptr;   // 2 x n words (two alternating buffers)
