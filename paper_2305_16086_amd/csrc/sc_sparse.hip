@@ -483,6 +483,8 @@ size_t carve(unsigned char* base, int64_t n, int64_t S2, int W, int64_t P, SrcBu
   take(&b.Q, sizeof(uint64_t) * 2 * static_cast<size_t>(W) * n);
   take(&b.S, sizeof(int32_t) * 2 * static_cast<size_t>(W) * n);
   b.part_capacity = kStaticPartCapacity;
+  if (const char* c = std::getenv("SC_SOURCE_PART_CAPACITY"))   // smaller buffer (tests)
+    b.part_capacity = std::max<int64_t>(1, std::min<int64_t>(kStaticPartCapacity, std::atoll(c)));
   b.W = W;
   return off;
 }

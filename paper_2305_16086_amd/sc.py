@@ -350,10 +350,20 @@ def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = No
     sources.  Returns (out, stats dict)."""
     o = options if options is not None else sc_default_options()
     src_arr = None
+    # the source list is this call's own: the caller's options keep what they held
+    # (a pointer to the temporary array must not outlive the call)
+    saved_sources = (o.sources, o.nsources)
     if sources is not None:
         src_arr = np.ascontiguousarray(sources, dtype=np.int32)
         o.sources = src_arr.ctypes.data
         o.nsources = len(src_arr)
+    try:
+        return _all_edges_ex_call(g, eps, L, o, out, tau_out, tilde_tau_out, nr_out)
+    finally:
+        o.sources, o.nsources = saved_sources
+
+
+def _all_edges_ex_call(g, eps, L, o, out, tau_out, tilde_tau_out, nr_out):
     device = out is not None and not isinstance(out, np.ndarray)
     if out is None:
         out = np.empty(g.m, dtype=np.float64)

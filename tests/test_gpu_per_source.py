@@ -199,10 +199,30 @@ def test_many_waves_and_walk_fallback_agree(sc, monkeypatch):
     out, st, _, tt2, nr2 = run_ps(sc, graph, 0.03)
     np.testing.assert_array_equal(out, ref)
     np.testing.assert_array_equal(tt2, tt)
-    monkeypatch.setenv("SC_SOURCE_PART_CAPACITY", "1")            # walks one half per wave
+    monkeypatch.setenv("SC_SOURCE_PART_CAPACITY", "1")            # walk batches of one chunk
     out3, _, _, _, nr3 = run_ps(sc, graph, 0.03)
     np.testing.assert_array_equal(nr3, nr)
     np.testing.assert_allclose(out3, ref, atol=TOL, rtol=0)
+
+
+def test_options_keep_no_source_list(sc):
+    # a call with sources= leaves the caller's options as they were: reusing them
+    # without sources= runs every source
+    graph = gg.barabasi_albert(500, 4, 21)
+    n, u, v = graph
+    g = sc.sc_build_graph(n, u, v)
+    try:
+        o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, seed=77)
+        sc.sc_all_edges_ex(g, 0.03, 0, o, sources=np.arange(10, dtype=np.int32))
+        assert o.nsources == 0 and not o.sources
+        tt = np.empty(n, np.int32)
+        out, _ = sc.sc_all_edges_ex(g, 0.03, 0, o, tilde_tau_out=tt)
+        assert np.all(tt >= 0)
+        ref, _ = sc.sc_all_edges_ex(g, 0.03, 0, sc.sc_default_options(
+            method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, seed=77))
+        np.testing.assert_array_equal(out, ref)
+    finally:
+        g.free()
 
 
 def test_deterministic(sc):

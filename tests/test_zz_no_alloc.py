@@ -5,6 +5,7 @@ per-source run (sc_all_edges_ex with SC_PER_SOURCE) on the same inputs.
   estimates within 1e-12 of the allocating run (the same kernels and walks; the
   slot count and the walk-sum buffer differ, which only reorders sums), while
   any device allocation by the library would fail (a one-byte budget);
+* a one-chunk walk-sum buffer (the static call then walks one half per wave);
 * a graph whose buffers exceed the static array is refused with SC_EINVAL;
 * lambda* must be known beforehand (computing it allocates).
 """
@@ -49,6 +50,29 @@ def test_static_entry_point_matches_allocating_run_twice(sc, monkeypatch):
             assert st[k] == st_ref[k], k
         assert tt.cpu().numpy().min() == st["tilde_min"]
         g.free()
+
+
+def test_static_entry_point_walk_fallback(sc, monkeypatch):
+    # a walk-sum buffer of one chunk: the static call walks one half per wave
+    import torch
+    n, u, v = gg.tree_plus_gnp(500, 8.0, 8)
+    print(f"[gpu] static entry, one-chunk walk buffer, n={n} m={len(u)}", flush=True)
+    g = sc.sc_build_graph(n, u, v)
+    sc.sc_lambda_star(g)
+    ref, st_ref = sc.sc_all_edges_ex(
+        g, 0.03, 0, sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, seed=5))
+    assert st_ref["walks"] > 0
+    out = torch.full((len(u),), -1.0, dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("SC_SOURCE_PART_CAPACITY", "1")
+    monkeypatch.setenv("SC_DEVICE_BYTES_LIMIT", "1")
+    _, st = sc.sc_all_edges_static(g, 0.03, 0, sc.sc_default_options(method=sc.SC_TGT_PLUS, seed=5),
+                                   out)
+    torch.cuda.synchronize()
+    monkeypatch.delenv("SC_DEVICE_BYTES_LIMIT")
+    monkeypatch.delenv("SC_SOURCE_PART_CAPACITY")
+    assert st["walks"] == st_ref["walks"]
+    np.testing.assert_allclose(out.cpu().numpy(), ref, atol=1e-12, rtol=0)
+    g.free()
 
 
 def test_static_entry_point_refuses_too_large_graph(sc):
