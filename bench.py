@@ -719,6 +719,46 @@ WEIGHTS = os.path.join(ROOT, "paper_2305_16086_amd", "weights", "closure_ba_gnp.
 BATCH_GOLDEN = os.path.join(ROOT, "tests", "golden", "batch_256_seed7_sampled_sc.npz")
 
 
+def library_spmm_reference(graph, dev, reps=20):
+    """The dense step's product D^-1 A Y by the vendor library: torch.sparse.mm on a
+    CSR tensor (hipSPARSE SpMM) with a random n x 64 FP32 block, run alone on the
+    GPU; mean time per product over `reps` runs by CUDA events.  A reference point
+    for the dense-step kernel, which computes the same product (plus the fused
+    accumulation) inside the pipeline.  None when the library call is unavailable."""
+    import torch
+    try:
+        n, u, v = graph
+        uu = np.concatenate([u, v]).astype(np.int64)
+        vv = np.concatenate([v, u]).astype(np.int64)
+        order = np.lexsort((vv, uu))
+        uu, vv = uu[order], vv[order]
+        deg = np.bincount(uu, minlength=n)
+        rowptr = np.zeros(n + 1, np.int64)
+        np.cumsum(deg, out=rowptr[1:])
+        vals = (1.0 / deg[uu]).astype(np.float32)
+        A = torch.sparse_csr_tensor(torch.from_numpy(rowptr).to(dev), torch.from_numpy(vv).to(dev),
+                                    torch.from_numpy(vals).to(dev), size=(n, n))
+        Y = torch.rand(n, 64, dtype=torch.float32, device=dev, generator=torch.Generator(
+            device=dev).manual_seed(5))
+        for _ in range(3):
+            Z = torch.sparse.mm(A, Y)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            Z = torch.sparse.mm(A, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        del Z, Y, A
+        return {"kernel": "torch.sparse.mm (hipSPARSE SpMM) of the same D^-1 A by a random "
+                          "n x 64 FP32 block, alone on the GPU",
+                "us": us, "gathered_TBps": len(uu) * 64 * 4 / (us * 1e-6) / 1e12}
+    except Exception as e:   # the library path is a reference only
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def plain_extras(a, sc, g, graph, out, stream):
     """The comparisons the metric names, on the same resident graph and the same
     2048 sampled exact values: the learned closure (committed weights) and plain
@@ -1077,8 +1117,10 @@ def main():
     last = step(traces={"tau_out": tau, "tilde_tau_out": tt, "nr_out": nr})
     torch.cuda.synchronize()
     extras = {}
+    spmm_ref = None
     if not a.no_extras:
         extras = plain_extras(a, sc, g, graph, out, stream)
+        spmm_ref = library_spmm_reference(graph, dev)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(graph, tau.cpu().numpy(), tt.cpu().numpy(), nr.cpu().numpy(),
@@ -1124,6 +1166,8 @@ def main():
             "launches": launches,
             "timed_launches": timed,
             "alg_bytes_per_launch": bytes_per_launch,
+            "gathered_TBps": 2 * m * 64 * 4 / (avg_launch_us * 1e-6) / 1e12 if launches else None,
+            "library_spmm": spmm_ref,
         },
         "cpu_baseline": cpu,
     }
