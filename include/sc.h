@@ -174,6 +174,23 @@ void sc_free_graph(sc_graph* g);
  */
 int sc_lambda_star(sc_graph* g, double* lam);
 
+/*
+ * Walk trace (a check of the walk stream, not part of a run): the nodes that
+ * walk pair r of half-edge (i -> j) visits over `length` steps, exactly as the
+ * TGT+ walk kernels take them (Algorithm 4's walks, estimator of Eq. 11).
+ * Step t of the walk from side s (0: from i, 1: from j) draws word (t-1) mod 4
+ * of Philox4x32-10 with counter (i, j, r, s * 2^31 + floor((t-1)/4)) and key
+ * (seed mod 2^32, seed / 2^32), and moves to neighbour floor(word * d / 2^32)
+ * of the current node's row (neighbours in ascending id order).
+ * nodes_host (host, 2 * length int32, caller-owned): nodes_host[t-1] is the
+ * node after step t from i, nodes_host[length + t-1] the same from j.
+ * i and j need not be adjacent.  Errors: SC_EINVAL for ids out of range,
+ * r outside [0, 2^32), length outside [0, 2^20]; SC_ENOMEM / SC_EHIP from the
+ * device (nodes_host is then not written).
+ */
+int sc_walk_trace(sc_graph* g, int32_t i, int32_t j, int64_t r, int32_t length, uint64_t seed,
+                  int32_t* nodes_host);
+
 /* ---- spectrum for CalTau (Algorithm 1, Theorem 3.2, Eq. 6-8) ----------------
  * The omega eigenpairs (lambda_k, phi_k) of N = D^-1/2 A D^-1/2 of largest
  * |lambda|: lambda[0] = 1 with phi_0 = sqrt(d / 2m), then |lambda| descending.

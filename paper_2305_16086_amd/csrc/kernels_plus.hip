@@ -899,6 +899,36 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
   return launch_walk_finish(f, st);
 }
 
+// The nodes visited by walk pair r of half-edge (i, j): thread 0 walks from i
+// (side 0), thread 1 from j (side 1), with the counters and the neighbour pick
+// of the walk kernels; nodes[side * len + t] is the node after step t + 1.
+__global__ void k_walk_trace(int i, int j, unsigned r, int len, unsigned k0, unsigned k1,
+                             const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             int32_t* __restrict__ nodes) {
+  const int side = threadIdx.x;
+  if (side > 1) return;
+  int pos = side == 0 ? i : j;
+  for (int t4 = 0; t4 < len; t4 += 4) {
+    const U32x4 w = philox4x32_10(static_cast<uint32_t>(i), static_cast<uint32_t>(j), r,
+                                  (side ? (1u << 31) : 0u) | static_cast<uint32_t>(t4 >> 2), k0, k1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (t4 + u >= len) break;
+      const int b = rowptr[pos], e = rowptr[pos + 1];
+      pos = col[b + static_cast<int>(pick_neighbour(w.w[u], static_cast<uint32_t>(e - b)))];
+      nodes[static_cast<size_t>(side) * len + t4 + u] = pos;
+    }
+  }
+}
+
+hipError_t launch_walk_trace(const DeviceGraph& g, int i, int j, uint32_t r, int len,
+                             uint64_t seed, int32_t* nodes, hipStream_t st) {
+  const unsigned k0 = static_cast<unsigned>(seed & 0xFFFFFFFFull);
+  const unsigned k1 = static_cast<unsigned>(seed >> 32);
+  k_walk_trace<<<1, 64, 0, st>>>(i, j, r, len, k0, k1, g.rowptr, g.col, nodes);
+  return hipGetLastError();
+}
+
 hipError_t launch_walk_finish(const FinishJob& f, hipStream_t st) {
   if (!f.gacc || f.kend <= f.kbeg) return hipSuccess;
   k_walk_finish<<<grid_for(f.kend - f.kbeg, 256), 256, 0, st>>>(f);

@@ -852,6 +852,33 @@ extern "C" int sc_lambda_star(sc_graph* g, double* lam) {
   return sc::graph_lambda_star(g, nullptr, lam);
 }
 
+extern "C" int sc_walk_trace(sc_graph* g, int32_t i, int32_t j, int64_t r, int32_t length,
+                             uint64_t seed, int32_t* nodes_host) {
+  if (!g || (!nodes_host && length > 0)) return fail(SC_EINVAL, "NULL argument");
+  if (i < 0 || j < 0 || i >= g->d.n || j >= g->d.n) return fail(SC_EINVAL, "node id out of range");
+  if (r < 0 || r > 0xFFFFFFFFll) return fail(SC_EINVAL, "walk index must lie in [0, 2^32)");
+  if (length < 0 || length > (1 << 20)) return fail(SC_EINVAL, "length must lie in [0, 2^20]");
+  if (length == 0) return SC_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != g->device) (void)hipSetDevice(g->device);
+  int32_t* d = nullptr;
+  int rc = SC_OK;
+  {
+    auto body = [&]() -> int {
+      HIP_TRY(sc::dev_alloc(&d, 2 * static_cast<size_t>(length)));
+      HIP_TRY(sc::launch_walk_trace(g->d, i, j, static_cast<uint32_t>(r), length, seed, d, nullptr));
+      HIP_TRY(hipMemcpy(nodes_host, d, 2 * static_cast<size_t>(length) * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+      return SC_OK;
+    };
+    rc = body();
+  }
+  sc::dev_free(d);
+  if (cur != g->device) (void)hipSetDevice(cur);
+  return rc;
+}
+
 // ====================================================================== all-edge SC
 
 extern "C" void sc_default_options(sc_options* o) {

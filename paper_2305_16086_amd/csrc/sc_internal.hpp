@@ -259,6 +259,10 @@ hipError_t launch_walks(const DeviceGraph& g, int kbeg, int kend, int s0, int B,
                         const int64_t* nr_slot, double* gacc, const WalkScratch& ws,
                         hipStream_t st, FinishJob* defer = nullptr);
 hipError_t launch_walk_finish(const FinishJob& job, hipStream_t st);
+// the nodes of walk pair r of half-edge (i, j) over len steps: nodes[0, len)
+// from i, nodes[len, 2 len) from j (device memory)
+hipError_t launch_walk_trace(const DeviceGraph& g, int i, int j, uint32_t r, int len,
+                             uint64_t seed, int32_t* nodes, hipStream_t st);
 
 // out[e] = gacc[slot(u_e->v_e)] + gacc[slot(v_e->u_e)] (Algorithm 2 line 12).
 hipError_t launch_combine(const DeviceGraph& g, const double* gacc, double* out,

@@ -120,6 +120,9 @@ def _load():
     lib.sc_graph_size.restype = C.c_int
     lib.sc_free_graph.argtypes = [C.c_void_p]
     lib.sc_free_graph.restype = None
+    lib.sc_walk_trace.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                  C.c_uint64, C.c_void_p]
+    lib.sc_walk_trace.restype = C.c_int
     lib.sc_lambda_star.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
     lib.sc_lambda_star.restype = C.c_int
     lib.sc_compute_spectrum.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double,
@@ -198,6 +201,7 @@ _lib = _load()
 
 # names declared in include/sc.h, for the export check
 EXPORTED = ["sc_default_options", "sc_build_graph", "sc_graph_size", "sc_free_graph",
+            "sc_walk_trace",
             "sc_lambda_star", "sc_all_edges", "sc_all_edges_ex", "sc_strerror",
             "sc_last_error", "sc_version", "sc_default_train_options", "sc_mlp_create",
             "sc_mlp_free", "sc_mlp_get", "sc_mlp_set", "sc_closure_dataset",
@@ -339,6 +343,16 @@ def _ptr(x):
     if isinstance(x, np.ndarray):
         return x.ctypes.data
     return x.data_ptr()  # torch tensor
+
+
+def sc_walk_trace(g: Graph, i: int, j: int, r: int, length: int, seed: int):
+    """Nodes visited by walk pair r of half-edge (i -> j): returns (from_i, from_j),
+    two int32 arrays of `length` nodes (include/sc.h)."""
+    nodes = np.empty(2 * max(int(length), 0), dtype=np.int32)
+    rc = _lib.sc_walk_trace(g.handle, int(i), int(j), int(r), int(length),
+                            int(seed) & 0xFFFFFFFFFFFFFFFF, nodes.ctypes.data)
+    _check(rc, "sc_walk_trace")
+    return nodes[:length], nodes[length:]
 
 
 def sc_all_edges_ex(g: Graph, eps: float, L: int, options: ScOptions | None = None, out=None,
