@@ -103,6 +103,43 @@ def test_eq14_switch_and_replay(sc, name, eps):
         assert np.abs(out - ex.sc_pinv(n, u, v)).max() <= eps
 
 
+def test_rmat_heterogeneous_switch(sc):
+    # a small R-MAT component: hubs next to many low-degree nodes, so Eq. 14 stops
+    # the sources at different switch steps (1..7 here)
+    graph = gg.rmat_lcc(10, 8, seed=3)
+    n, u, v = graph
+    out, st, tau, tt, nr = run_ps(sc, graph, 0.05)
+    assert st["tilde_max"] - st["tilde_min"] >= 3
+    assert len(np.unique(tt)) >= 4
+    check_against_oracle(graph, 0.05, out, st, tau, tt, nr)
+    if st["L_capped"] == 0:
+        assert np.abs(out - ex.sc_pinv(n, u, v)).max() <= 0.05
+
+
+def test_rmat_scale22_sampled_exact(sc):
+    # the R-MAT scale-22 benchmark graph at its full size, per-source TGT+ at
+    # eps = 1e-2 as the benchmark runs it, on the endpoints of 40 of the 512 edges
+    # whose exact SC the oracle stored (every 13th)
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "rmat22_seed22_sampled_sc.npz")
+    gz = np.load(path)
+    n, u, v = gg.rmat_lcc(22, 16, seed=22)
+    assert n == int(gz["n"]) and len(u) == int(gz["m"])
+    ids = gz["edge_ids"]
+    sel = ids[::13]
+    want = gz["sc"][::13]
+    ends = np.unique(np.concatenate([u[sel], v[sel]])).astype(np.int32)
+    print(f"[gpu] rmat22 n={n} m={len(u)} sources={len(ends)}", flush=True)
+    g = sc.sc_build_graph(n, u, v)
+    try:
+        o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE)
+        out, st = sc.sc_all_edges_ex(g, 1e-2, 0, o, sources=ends)
+        assert st["L_capped"] == 0 and st["lambda_converged"] == 1
+        assert np.abs(out[sel] - want).max() <= 1e-2
+    finally:
+        g.free()
+
+
 @pytest.mark.parametrize("gamma", [0, 1, 3, 40, 1000])
 def test_gamma_range(sc, gamma):
     graph = gg.barabasi_albert(250, 3, 9)

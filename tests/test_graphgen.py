@@ -46,3 +46,20 @@ def test_er_series_sizes():
     assert gg.ER_EDGES_SERIES == [(10_000, m) for m in (200_000, 500_000, 1_000_000, 2_000_000,
                                                         5_000_000)]
     assert gg.ER_NODES_SERIES == [(n, 1_000_000) for n in (2_000, 5_000, 10_000, 20_000, 50_000)]
+
+
+def test_rmat_lcc_simple_connected_seeded_heavy_tailed():
+    a = gg.rmat_lcc(12, 16, seed=22)
+    b = gg.rmat_lcc(12, 16, seed=22)
+    c = gg.rmat_lcc(12, 16, seed=23)
+    n, u, v = a
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]) and a[0] == b[0]
+    assert not (a[0] == c[0] and np.array_equal(a[1][:100], c[1][:100]))
+    assert n <= 1 << 12 and n > (1 << 12) // 2
+    assert simple_edges(n, u, v)
+    assert gg.is_connected(n, u, v)
+    d = gg.degrees(n, u, v)
+    # (a, b, c, d) = (.57, .19, .19, .05) skews the degrees: a hub far above the mean
+    assert d.max() > 20 * d.mean()
+    # at most 16 * 2^12 generated edges survive symmetrising and deduplication
+    assert len(u) <= 16 * (1 << 12)
