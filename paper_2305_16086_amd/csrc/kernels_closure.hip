@@ -12,7 +12,7 @@
 // float vector: W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3.
 // Training (FP32): per-workgroup forward/backward on 64-sample tiles, partial
 // gradients reduced in a fixed order, Adam.  Inference: BF16 MFMA
-// (v_mfma_f32_16x16x16_bf16) with FP32 accumulation.
+// (gfx950's v_mfma_f32_16x16x32_bf16) with FP32 accumulation.
 #include "sc_internal.hpp"
 
 #include <hip/hip_bf16.h>
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer_f32(const float* __restrict__
   y[i] = out;
 }
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // LDS hand-off between lanes of one wave (no workgroup barrier: waves iterate independently)
@@ -382,6 +382,8 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+__device__ inline __bf16 as_bf16(short bits) { return __builtin_bit_cast(__bf16, bits); }
 
 __device__ inline short to_bf16(float v) {
   // round to nearest even
@@ -392,11 +394,13 @@ __device__ inline short to_bf16(float v) {
 }
 
 // BF16 MFMA path.  One wave handles 16 samples per iteration; layer products
-// use v_mfma_f32_16x16x16_bf16 with the operand layout
-//   A (16 x 16, row-major i,k): lane l supplies A[l%16][4*(l/16) .. +3]
-//   B (16 x 16, k,j):           lane l supplies B[4*(l/16) .. +3][l%16]
+// use v_mfma_f32_16x16x32_bf16 with the operand layout
+//   A (16 x 32, row-major i,k): lane l supplies A[l%16][8*(l/16) .. +7]
+//   B (32 x 16, k,j):           lane l supplies B[8*(l/16) .. +7][l%16]
 //   D (16 x 16):                lane l holds D[4*(l/16) .. +3][l%16]
-// Activations move from the D layout to the A layout through LDS.
+// Layer 1 (16 inputs) fills the upper half of k with zeros; layer 2 (64
+// hidden inputs) takes two k-blocks of 32.  Activations move from the D layout
+// to the A layout through LDS.
 __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const float* __restrict__ theta,
                                                         const float* __restrict__ norm,
                                                         const float* __restrict__ X, int64_t N,
@@ -422,24 +426,26 @@ __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const float* __restrict_
   for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wv; tile < ntiles;
        tile += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
     const int64_t base = tile * 16;
-    // layer 1: A = normalised X tile (16 x 16), B = W1^T (16 x 64) in four 16-column blocks
-    bf16x4_t ax;
+    // layer 1: A = normalised X tile (16 x 16, k padded to 32 with zeros),
+    // B = W1^T (16 x 64) in four 16-column blocks
+    bf16x8_t ax;
     {
       const int64_t s = base + li;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 4 * lk + q;
-        const float v = s < N ? (X[s * kIn + f] - norm[f]) * norm[kIn + f] : 0.0f;
-        ax[q] = to_bf16(v);
+      for (int q = 0; q < 8; ++q) {
+        const int f = 8 * lk + q;
+        const float v = s < N && f < kIn ? (X[s * kIn + f] - norm[f]) * norm[kIn + f] : 0.0f;
+        ax[q] = as_bf16(to_bf16(v));
       }
     }
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
-      bf16x4_t bw;
+      bf16x8_t bw;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bw[q] = sW1[(nb * 16 + li) * kIn + 4 * lk + q];
+      for (int q = 0; q < 8; ++q)
+        bw[q] = as_bf16(8 * lk + q < kIn ? sW1[(nb * 16 + li) * kIn + 8 * lk + q] : short(0));
       f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bw, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, bw, acc, 0, 0, 0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int o = nb * 16 + li;
@@ -452,16 +458,17 @@ __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const float* __restrict_
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc2[nb] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      bf16x4_t ah;
+    for (int kb = 0; kb < 2; ++kb) {
+      bf16x8_t ah;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ah[q] = to_bf16(sAct[wv][li][kb * 16 + 4 * lk + q]);
+      for (int q = 0; q < 8; ++q) ah[q] = as_bf16(to_bf16(sAct[wv][li][kb * 32 + 8 * lk + q]));
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        bf16x4_t bw;
+        bf16x8_t bw;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bw[q] = sW2[(nb * 16 + li) * kHid + kb * 16 + 4 * lk + q];
-        acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bw, acc2[nb], 0, 0, 0);
+        for (int q = 0; q < 8; ++q)
+          bw[q] = as_bf16(sW2[(nb * 16 + li) * kHid + kb * 32 + 8 * lk + q]);
+        acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw, acc2[nb], 0, 0, 0);
       }
     }
     wave_sync();
