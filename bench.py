@@ -75,6 +75,8 @@ def parse():
     p.add_argument("--rmat-scale", type=int, default=22, help="rmat: R-MAT scale")
     p.add_argument("--orkut-eps", type=float, default=1e-3,
                    help="orkut: error bound eps (at 1e-2 lambda* = 0.23 keeps tau at 1)")
+    p.add_argument("--switch-rule", type=int, default=0, choices=[0, 1],
+                   help="rmat, orkut: Eq. 14 as printed (0) or weighing walks by their steps (1)")
     p.add_argument("--full-call-limit", type=float, default=150.0,
                    help="rmat, orkut: time the whole call when the sample extrapolates below this (s)")
     p.add_argument("--rmat-sources", type=int, default=4096,
@@ -920,14 +922,15 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
     print(f"[{name}] built {build_s:.1f} s, lambda* {lam:.4f} ({lam_s:.1f} s)", file=sys.stderr,
           flush=True)
     out = torch.empty(m, dtype=torch.float64, device=dev)
-    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, stream=stream.cuda_stream)
+    o = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE, stream=stream.cuda_stream,
+                              switch_rule=a.switch_rule)
     rng = np.random.default_rng(22)
     src = rng.choice(n, size=min(a.rmat_sources, n), replace=False).astype(np.int32)
     sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src[:256])   # buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ot = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE | sc.SC_TIME_KERNELS,
-                               stream=stream.cuda_stream)
+                               stream=stream.cuda_stream, switch_rule=a.switch_rule)
     _, st = sc.sc_all_edges_ex(g, eps, 0, ot, out=out, sources=src)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -988,8 +991,10 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
         "ms_per_step": 1e3 * call_s, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "u64 fixed point + f64", "data": "synthetic",
         "config": {
-            "workload": f"{workload}: n={n}, m={m}; TGT+ per source (Eq. 14 switch), eps={eps}, "
-                        f"lambda*-bound truncation at eps/2",
+            "workload": f"{workload}: n={n}, m={m}; TGT+ per source ("
+                        + ("Eq. 14 switch" if a.switch_rule == 0 else
+                           "switch by Eq. 14 with walks weighed by their steps") +
+                        f"), eps={eps}, lambda*-bound truncation at eps/2",
             "sample": (f"{len(src)} uniform random sources timed in one call ({dt:.2f} s) "
                        f"extrapolated by n/{len(src)} to {full_s:.1f} s" +
                        ("; the whole call then timed (value)" if full else
