@@ -286,7 +286,7 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   if (budget == 0) {
     size_t fr = 0, tot = 0;
     HIP_TRY(hipMemGetInfo(&fr, &tot));
-    budget = std::min<size_t>(fr / 3, size_t(48) << 30);
+    budget = std::min<size_t>(fr / 2, size_t(128) << 30);
   }
   SrcBufs B;
   B.W = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(kMaxSlots), nsrc,
