@@ -373,12 +373,15 @@ def test_blocks_without_traversal_are_skipped_correctly(sc, precision):
         np.testing.assert_allclose(out[both], ref[both], atol=tol, rtol=0)
 
 
-@pytest.mark.parametrize("nblocks", [2, 3, 4, 7])
+@pytest.mark.parametrize("nblocks", [2, 3, 4, 7, 13, 26])
 def test_tgt_plus_pipeline_depths(sc, nblocks):
-    """Source blocks cycle through three state pairs, each reused once the tail
-    of the block three back is done: graphs of 2, 3, 4 and 7 blocks (the last
-    one ragged) against the oracle's replay on every edge."""
-    n = 64 * nblocks - (17 if nblocks == 7 else 0)
+    """The two streams meet once per group of four blocks and the groups cycle
+    through three sets of four state pairs, a set reused once the tails of the
+    group three back are done: graphs of 2 to 26 blocks (within one group, one
+    set, past the first reuse at 13, several reuses and a ragged last group at
+    26; the last block ragged at 7 and 26) against the oracle's replay on every
+    edge."""
+    n = 64 * nblocks - (17 if nblocks in (7, 26) else 0)
     graph = gg.barabasi_albert(n, 3, 40 + nblocks)
     n, u, v = graph
     m = len(u)
