@@ -79,6 +79,9 @@ def parse():
                    help="rmat, orkut: Eq. 14 as printed (0) or weighing walks by their steps (1)")
     p.add_argument("--full-call-limit", type=float, default=150.0,
                    help="rmat, orkut: time the whole call when the sample extrapolates below this (s)")
+    p.add_argument("--degree-order", type=int, default=None, choices=[0, 1],
+                   help="build the graph with SC_DEGREE_ORDER (nodes stored by descending "
+                        "degree); default: on for rmat and orkut, off for plain")
     p.add_argument("--rmat-sources", type=int, default=4096,
                    help="rmat: uniform random sources timed (the full call is extrapolated)")
     p.add_argument("--no-extras", action="store_true",
@@ -913,8 +916,9 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
     n, u, v = graph
     m = len(u)
     print(f"[{name}] n={n} m={m} ({gen_s:.0f} s)", file=sys.stderr, flush=True)
+    degree_order = a.degree_order is None or a.degree_order == 1
     t0 = time.perf_counter()
-    g = sc.sc_build_graph(n, u, v)
+    g = sc.sc_build_graph(n, u, v, sc.SC_DEGREE_ORDER if degree_order else 0)
     build_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     lam = sc.sc_lambda_star(g)
@@ -1000,6 +1004,8 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
                        ("; the whole call then timed (value)" if full else
                         "; the value is the extrapolation")),
             "full_call": full,
+            "node_order": ("degree (SC_DEGREE_ORDER: stored by descending degree, the "
+                           "caller's ids at the interface)" if degree_order else "the generator's"),
             "sample_sources_per_s": len(src) / dt, "lambda_star": lam,
             "lambda_converged": st["lambda_converged"], "L_used": st["L_used"],
             "L_min": st["L_min"], "L_capped": st["L_capped"], "tilde_min": st["tilde_min"],
@@ -1063,7 +1069,7 @@ def main():
     m = len(u)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    g = sc.sc_build_graph(n, u, v)
+    g = sc.sc_build_graph(n, u, v, sc.SC_DEGREE_ORDER if a.degree_order == 1 else 0)
     out = torch.empty(m, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
@@ -1150,6 +1156,7 @@ def main():
                         "FP64 per-edge sums, block 64",
             "max_abs_err_sampled": err,
             "err_sample": "2048 edges, exact SC by float64 block-PCG" if err is not None else None,
+            "node_order": "degree (SC_DEGREE_ORDER)" if a.degree_order == 1 else "the generator's",
             "L_used": last["L_used"], "L_min": last["L_min"],
             "tilde_tau": last["tilde_tau"], "lambda_star": last["lambda_star"],
             "lambda_converged": last["lambda_converged"], "L_capped": last["L_capped"],

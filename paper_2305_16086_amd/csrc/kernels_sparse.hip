@@ -756,6 +756,19 @@ hipError_t launch_src_clear(const SrcWalkArgs& a, int nslots_used, hipStream_t s
   return hipGetLastError();
 }
 
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ idx,
+                             int32_t* __restrict__ dst, int64_t n) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < n) dst[x] = src[idx[x]];
+}
+
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t* dst, int64_t n,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_gather_i32<<<static_cast<unsigned>((n + 255) / 256), 256, 0, st>>>(src, idx, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st) {
   hipError_t e = launch_src_scan(a, st);
   if (e == hipSuccess) e = launch_src_walk_batch(a, st);

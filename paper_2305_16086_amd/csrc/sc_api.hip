@@ -93,6 +93,7 @@ void sc_graph::release() {
   dev_free(d.wg_tasks);
   dev_free(d.ptasks);
   dev_free(d.giant);
+  dev_free(rank_d);
   for (auto& y : Y) {
     if (y) (void)sc::tracked_free(y);
     y = nullptr;
@@ -367,9 +368,60 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
   *out = nullptr;
   sc::HostCSR h;
-  const int rc = sc::build_host_csr(n, m, u, v, flags, h);
+  bool ranges_ok = (flags & SC_DEGREE_ORDER) && u && v && n >= 2 && n < (1ll << 31) && m >= 1 &&
+                   2 * m < (1ll << 31);
+  for (int64_t e = 0; ranges_ok && e < m; ++e)
+    ranges_ok = u[e] >= 0 && u[e] < n && v[e] >= 0 && v[e] < n;
+  if (!ranges_ok) {
+    // the caller's ids (or input errors, reported by the build)
+    const int rc = sc::build_host_csr(n, m, u, v, flags & ~SC_DEGREE_ORDER, h);
+    if (rc) return rc;
+    return sc::graph_from_csr(h, out);
+  }
+  // renumber by descending degree, ties by ascending id; the edge order is kept
+  std::vector<int32_t> rank, label;
+  std::vector<int64_t> u2, v2;
+  try {
+    std::vector<int64_t> deg(n, 0);
+    for (int64_t e = 0; e < m; ++e) {
+      ++deg[u[e]];
+      ++deg[v[e]];
+    }
+    label.resize(n);
+    std::iota(label.begin(), label.end(), 0);
+    std::stable_sort(label.begin(), label.end(),
+                     [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    rank.resize(n);
+    for (int64_t y = 0; y < n; ++y) rank[label[y]] = static_cast<int32_t>(y);
+    u2.resize(m);
+    v2.resize(m);
+    for (int64_t e = 0; e < m; ++e) {
+      u2[e] = rank[u[e]];
+      v2[e] = rank[v[e]];
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(SC_ENOMEM, "host allocation failed");
+  }
+  int rc = sc::build_host_csr(n, m, u2.data(), v2.data(), flags & ~SC_DEGREE_ORDER, h);
   if (rc) return rc;
-  return sc::graph_from_csr(h, out);
+  u2 = std::vector<int64_t>();
+  v2 = std::vector<int64_t>();
+  sc_graph* g = nullptr;
+  rc = sc::graph_from_csr(h, &g);
+  if (rc) return rc;
+  const hipError_t e = sc::dev_alloc(&g->rank_d, static_cast<size_t>(n));
+  const hipError_t e2 = e == hipSuccess ? hipMemcpy(g->rank_d, rank.data(), n * sizeof(int32_t),
+                                                    hipMemcpyHostToDevice)
+                                        : e;
+  if (e2 != hipSuccess) {
+    sc_free_graph(g);
+    return fail(e2 == hipErrorOutOfMemory ? SC_ENOMEM : SC_EHIP,
+                std::string("graph upload: ") + hipGetErrorString(e2));
+  }
+  g->rank_h = std::move(rank);
+  g->label_h = std::move(label);
+  *out = g;
+  return SC_OK;
 }
 
 extern "C" int sc_graph_size(const sc_graph* g, int64_t* n, int64_t* m) {
@@ -806,12 +858,25 @@ extern "C" int sc_set_spectrum(sc_graph* g, int omega, const double* lambda, con
   (void)hipGetDevice(&cur);
   if (cur != g->device) (void)hipSetDevice(g->device);
   const size_t cells = static_cast<size_t>(g->d.n) * omega;
+  std::vector<double> stored;   // rows in the stored node order (renumbered graphs)
+  if (!g->rank_h.empty()) {
+    try {
+      stored.resize(cells);
+    } catch (const std::bad_alloc&) {
+      if (cur != g->device) (void)hipSetDevice(cur);
+      return fail(SC_ENOMEM, "host allocation failed");
+    }
+    for (int64_t x = 0; x < g->d.n; ++x)
+      std::memcpy(stored.data() + static_cast<size_t>(g->rank_h[x]) * omega,
+                  phi + static_cast<size_t>(x) * omega, omega * sizeof(double));
+  }
+  const double* phi_src = stored.empty() ? phi : stored.data();
   double* lam_d = nullptr;
   double* phi_d = nullptr;
   hipError_t e = sc::dev_alloc(&lam_d, omega);
   if (e == hipSuccess) e = sc::dev_alloc(&phi_d, cells);
   if (e == hipSuccess) e = hipMemcpy(lam_d, lambda, omega * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(phi_d, phi, cells * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(phi_d, phi_src, cells * sizeof(double), hipMemcpyHostToDevice);
   if (cur != g->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) {
     sc::dev_free(lam_d);
@@ -835,14 +900,27 @@ extern "C" int sc_get_spectrum(const sc_graph* g, int* omega, double* lambda, do
   if (g->spec_omega == 0) return SC_OK;
   if (lambda) std::memcpy(lambda, g->spec_lam_h.data(), g->spec_omega * sizeof(double));
   if (phi) {
+    const int omega_s = g->spec_omega;
+    const size_t cells = static_cast<size_t>(g->d.n) * omega_s;
+    std::vector<double> stored;   // rows in the stored node order (renumbered graphs)
+    if (!g->rank_h.empty()) {
+      try {
+        stored.resize(cells);
+      } catch (const std::bad_alloc&) {
+        return fail(SC_ENOMEM, "host allocation failed");
+      }
+    }
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
-    const hipError_t e = hipMemcpy(phi, g->spec_phi,
-                                   static_cast<size_t>(g->d.n) * g->spec_omega * sizeof(double),
-                                   hipMemcpyDeviceToHost);
+    const hipError_t e = hipMemcpy(stored.empty() ? phi : stored.data(), g->spec_phi,
+                                   cells * sizeof(double), hipMemcpyDeviceToHost);
     if (cur != g->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return fail(SC_EHIP, std::string("get spectrum: ") + hipGetErrorString(e));
+    for (int64_t x = 0; !stored.empty() && x < g->d.n; ++x)
+      std::memcpy(phi + static_cast<size_t>(x) * omega_s,
+                  stored.data() + static_cast<size_t>(g->rank_h[x]) * omega_s,
+                  omega_s * sizeof(double));
   }
   return SC_OK;
 }
@@ -859,6 +937,11 @@ extern "C" int sc_walk_trace(sc_graph* g, int32_t i, int32_t j, int64_t r, int32
   if (r < 0 || r > 0xFFFFFFFFll) return fail(SC_EINVAL, "walk index must lie in [0, 2^32)");
   if (length < 0 || length > (1 << 20)) return fail(SC_EINVAL, "length must lie in [0, 2^20]");
   if (length == 0) return SC_OK;
+  const bool renumbered = !g->rank_h.empty();
+  if (renumbered) {   // the stored nodes
+    i = g->rank_h[i];
+    j = g->rank_h[j];
+  }
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != g->device) (void)hipSetDevice(g->device);
@@ -876,6 +959,8 @@ extern "C" int sc_walk_trace(sc_graph* g, int32_t i, int32_t j, int64_t r, int32
   }
   sc::dev_free(d);
   if (cur != g->device) (void)hipSetDevice(cur);
+  if (rc == SC_OK && renumbered)   // back to the caller's ids
+    for (int64_t t = 0; t < 2 * static_cast<int64_t>(length); ++t) nodes_host[t] = g->label_h[nodes_host[t]];
   return rc;
 }
 
@@ -1289,7 +1374,8 @@ int run_method(sc_graph* g, double eps, int L, const sc_options& o, double* out_
   std::vector<int32_t> tilde_h;
   if (o.tilde_tau_out) {
     tilde_h.resize(n);
-    for (int64_t x = 0; x < n; ++x) tilde_h[x] = plus ? tilde : tau_row[x];
+    for (int64_t x = 0; x < n; ++x)   // in the caller's ids
+      tilde_h[x] = plus ? tilde : tau_row[g->rank_h.empty() ? x : g->rank_h[x]];
     if (dev_ptrs)
       HIP_TRY(hipMemcpyAsync(o.tilde_tau_out, tilde_h.data(), n * sizeof(int32_t),
                              hipMemcpyHostToDevice, st));

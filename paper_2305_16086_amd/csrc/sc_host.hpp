@@ -75,6 +75,11 @@ struct sc_graph {
   int device = 0;
   std::vector<int32_t> rowptr_h;
   std::vector<int32_t> deg_h;
+  // SC_DEGREE_ORDER: the caller's node x is stored as rank_h[x]; stored node y is
+  // the caller's label_h[y] (both empty when the graph keeps the caller's ids)
+  std::vector<int32_t> rank_h;
+  std::vector<int32_t> label_h;
+  int32_t* rank_d = nullptr;            // device copy of rank_h
   double lambda_star = -1.0;
   int lambda_converged = -1;            // of the cached lambda* (see sc_stats)
   // spectrum for CalTau (Algorithm 1): spec_omega eigenpairs of D^-1/2 A D^-1/2,

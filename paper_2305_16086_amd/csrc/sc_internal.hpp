@@ -349,6 +349,10 @@ hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t s
 hipError_t launch_src_scan(const SrcWalkArgs& a, hipStream_t st);
 hipError_t launch_src_walk_batch(const SrcWalkArgs& a, hipStream_t st);
 hipError_t launch_src_clear(const SrcWalkArgs& a, int nslots_used, hipStream_t st);
+// dst[x] = src[idx[x]] for x < n (per-node results of a renumbered graph, in the
+// caller's ids)
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t* dst, int64_t n,
+                             hipStream_t st);
 
 // --------------------------------------------------------------- learned closure
 constexpr int kMlpParams = 5313;

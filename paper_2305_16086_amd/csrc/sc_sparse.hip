@@ -249,7 +249,7 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
       if (s < 0 || s >= n) return fail(SC_EINVAL, "source id out of range");
       if (seen[s]) return fail(SC_EINVAL, "source listed twice");
       seen[s] = 1;
-      order[k] = s;
+      order[k] = g->rank_h.empty() ? s : g->rank_h[s];   // the stored node
     }
   } else {
     for (int64_t k = 0; k < nsrc; ++k) order[k] = static_cast<int32_t>(k);
@@ -389,9 +389,20 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   const double host_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host0).count();
   HIP_TRY(hipEventRecord(t1, st));
-  if (o.tilde_tau_out)
-    HIP_TRY(hipMemcpyAsync(o.tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
-                           dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  const bool renumbered = g->rank_d != nullptr;
+  std::vector<int32_t> tilde_h;   // stored order, for a host output of a renumbered graph
+  if (o.tilde_tau_out) {
+    if (renumbered && dev_ptrs) {
+      HIP_TRY(sc::launch_gather_i32(B.tilde_row, g->rank_d, o.tilde_tau_out, n, st));
+    } else if (renumbered) {
+      tilde_h.resize(n);
+      HIP_TRY(hipMemcpyAsync(tilde_h.data(), B.tilde_row, n * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
+    } else {
+      HIP_TRY(hipMemcpyAsync(o.tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
+                             dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    }
+  }
   unsigned long long tot[kTotals] = {};
   HIP_TRY(hipMemcpyAsync(tot, B.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
   if (!dev_ptrs) {
@@ -403,6 +414,8 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   }
   HIP_TRY(hipStreamSynchronize(st));
   sb.clean = true;
+  if (!tilde_h.empty())
+    for (int64_t x = 0; x < n; ++x) o.tilde_tau_out[x] = tilde_h[g->rank_h[x]];
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
   if (st_user) {
@@ -551,9 +564,13 @@ extern "C" int sc_all_edges_static(sc_graph* g, double eps, int L, const sc_opti
   const auto host0 = std::chrono::steady_clock::now();
   rc = enqueue_per_source(g, eps, L, *o, lam, B, n, nullptr, out, o->tau_out, o->nr_out, stream);
   if (rc) return rc;
-  if (o->tilde_tau_out)
-    HIP_TRY(hipMemcpyAsync(o->tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, stream));
+  if (o->tilde_tau_out) {
+    if (g->rank_d)
+      HIP_TRY(sc::launch_gather_i32(B.tilde_row, g->rank_d, o->tilde_tau_out, n, stream));
+    else
+      HIP_TRY(hipMemcpyAsync(o->tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, stream));
+  }
   last.clean = true;   // in stream order, the walks' last pass clears every column it used
   if (st) {
     unsigned long long tot[kTotals] = {};

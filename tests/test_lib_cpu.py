@@ -60,6 +60,31 @@ def test_validation_rejects_invalid_graphs():
     assert "bipartite" in sc.sc_last_error()
 
 
+def test_validation_with_degree_order_reports_the_same_errors():
+    """SC_DEGREE_ORDER renumbers after the id checks: every invalid graph gets the
+    code it gets without the flag (edge indices in the caller's order)."""
+    from paper_2305_16086_amd import sc
+    f = sc.SC_DEGREE_ORDER
+    assert _code(3, [0, 1, 2], [1, 2, 2], f) == sc.SC_ESELFLOOP
+    assert "edge 2" in sc.sc_last_error()
+    assert _code(3, [0, 1, 0, 1], [1, 2, 2, 0], f) == sc.SC_EDUP
+    assert "edge 3" in sc.sc_last_error()
+    assert _code(3, [0, 1, 0], [1, 2, 3], f) == sc.SC_EINVAL
+    assert _code(3, [0, 1, -1], [1, 2, 2], f) == sc.SC_EINVAL
+    assert _code(1, [0], [0], f) == sc.SC_EINVAL
+    assert _code(6, [0, 1, 0, 3, 4, 3], [1, 2, 2, 4, 5, 5], f) == sc.SC_EDISCONNECTED
+    n, u, v = gg.cycle_graph(6)
+    assert _code(n, u, v, f) == sc.SC_EBIPARTITE
+
+
+def test_batch_rejects_degree_order():
+    from paper_2305_16086_amd import sc
+    with pytest.raises(sc.ScError) as ei:
+        sc.sc_build_batch([gg.complete_graph(4)], sc.SC_DEGREE_ORDER)
+    assert ei.value.code == sc.SC_EINVAL
+    assert "SC_DEGREE_ORDER" in sc.sc_last_error()
+
+
 def test_validation_of_even_cycle_plus_chord_is_not_bipartite_error():
     from paper_2305_16086_amd import sc
     # C6 plus a chord (0, 2) has a triangle; validation must not call it bipartite.
