@@ -281,7 +281,9 @@ int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double*
  * (unit 2^-63) and sums them with integer atomics, so results are
  * reproducible; precision and block are ignored.  Per-source columns take
  * 24 n bytes per workgroup slot (up to 2048 slots, within half the free
- * device memory and at most 128 GiB, or SC_SOURCE_SLOT_BYTES).  st: tilde_min / tilde_max,
+ * device memory, the handle's slot buffers from earlier calls counted as free,
+ * and at most 128 GiB, or SC_SOURCE_SLOT_BYTES); the handle keeps them for
+ * later calls until sc_free_graph.  st: tilde_min / tilde_max,
  * push_edges, walks, walk_steps; with SC_TIME_KERNELS, prop_ms is the time of
  * the waves' walk phases (events on the stream), prop_launches = prop_timed =
  * waves and prop_bytes = 20 bytes per single-walk step (row bounds, neighbour

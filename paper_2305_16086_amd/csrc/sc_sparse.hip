@@ -286,7 +286,10 @@ int sc::run_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   if (budget == 0) {
     size_t fr = 0, tot = 0;
     HIP_TRY(hipMemGetInfo(&fr, &tot));
-    budget = std::min<size_t>(fr / 2, size_t(128) << 30);
+    // the slot columns and lists the handle already holds are reused or
+    // replaced, so they count as free
+    const size_t held = g->src.qcap * (sizeof(uint64_t) + sizeof(int32_t));
+    budget = std::min<size_t>((fr + held) / 2, size_t(128) << 30);
   }
   SrcBufs B;
   B.W = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(kMaxSlots), nsrc,

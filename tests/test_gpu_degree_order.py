@@ -198,3 +198,30 @@ def test_within_eps_of_exact(sc, graph, pair):
     for eps, opt in ((1e-2, dict(method=1)), (1e-2, dict(method=1, flags=0x20))):
         out, *_ = run(sc, gf, n, len(u), eps, **opt)
         assert np.abs(out - exact).max() <= eps
+
+
+def test_learned_closure_and_dataset(sc, graph, pair):
+    import torch
+    n, u, v = graph
+    m = len(u)
+    gf, gr, rank, label = pair
+    print("[gpu] degree order: learned closure", flush=True)
+    data = []
+    for g in (gf, gr):
+        X = torch.empty(m * 16, dtype=torch.float32, device="cuda")
+        z = torch.empty(m, dtype=torch.float32, device="cuda")
+        w = torch.empty(m, dtype=torch.float32, device="cuda")
+        sc.sc_closure_dataset(g, 41, 1, X, z, w)
+        torch.cuda.synchronize()
+        data.append([t.cpu().numpy() for t in (X, z, w)])
+    for a, b in zip(*data):   # per edge, input order
+        assert np.array_equal(a, b)
+    net = sc.sc_mlp_create(5)
+    outs = []
+    for g in (gf, gr):
+        o = sc.sc_default_options(method=sc.SC_LEARNED, precision=0, mlp=net.handle.value)
+        out, st = sc.sc_all_edges_ex(g, 1e-2, 0, o)
+        outs.append((out, st["fallback_edges"]))
+    net.free()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
