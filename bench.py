@@ -37,10 +37,18 @@ PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
                         "paper_2305_16086_amd/csrc/accumulate.hpp"), "a7a719226577e17d")
 
 
-def traffic_source_digest():
+# Fabric bytes per single-walk step of the per-source walk kernel on R-MAT scale 22 with the
+# nodes in degree order (the timed 4,096-source call), from the same counters and scale
+# factors (profiles/hbm_rmat22_k_src_walks.md); valid only for the sources they were taken on
+WALK_TRAFFIC_BYTES_PER_STEP = 252.0
+WALK_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_sparse.hip",
+                        "paper_2305_16086_amd/csrc/philox.hpp"), "c4dac1d474bcc7a2")
+
+
+def traffic_source_digest(files=PROP_TRAFFIC_SOURCE[0]):
     import hashlib
     h = hashlib.sha256()
-    for rel in PROP_TRAFFIC_SOURCE[0]:
+    for rel in files:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -48,6 +56,11 @@ def traffic_source_digest():
 
 def measured_traffic():
     return PROP_TRAFFIC_BYTES if traffic_source_digest() == PROP_TRAFFIC_SOURCE[1] else None
+
+
+def measured_walk_traffic_per_step():
+    ok = traffic_source_digest(WALK_TRAFFIC_SOURCE[0]) == WALK_TRAFFIC_SOURCE[1]
+    return WALK_TRAFFIC_BYTES_PER_STEP if ok else None
 
 
 def parse():
@@ -930,7 +943,7 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
                               switch_rule=a.switch_rule)
     rng = np.random.default_rng(22)
     src = rng.choice(n, size=min(a.rmat_sources, n), replace=False).astype(np.int32)
-    sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src[:256])   # buffers
+    wst = sc.sc_all_edges_ex(g, eps, 0, o, out=out, sources=src[:256])[1]   # buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ot = sc.sc_default_options(method=sc.SC_TGT_PLUS, flags=sc.SC_PER_SOURCE | sc.SC_TIME_KERNELS,
@@ -988,6 +1001,10 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
         print(f"[{name}] error on {checked} sampled edges: max {err:.2e}", file=sys.stderr, flush=True)
     g.free()
     call_s = full["s"] if full else full_s
+    # counters were taken for the R-MAT sample in degree order only
+    per_step = (measured_walk_traffic_per_step()
+                if name == "rmat_s22" and degree_order and full is None else None)
+    walk_traffic = per_step * st["walk_steps"] if per_step else None
     line = {
         "metric": ("all-edge SC edges/sec (per-source TGT+, whole call)" if full else
                    "all-edge SC edges/sec (per-source TGT+, extrapolated from sampled sources)"),
@@ -1013,6 +1030,8 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
             "push_edges": st["push_edges"], "max_abs_err_sampled": err, "checked_edges": checked,
             "check_call": ck, "generate_s": gen_s, "build_s": build_s, "lambda_s": lam_s,
             "walk_phase_ms": st["prop_ms"], "call_ms": 1e3 * dt,
+            "warmup_call": {"sources": int(min(256, len(src))), "walks": wst["walks"],
+                            "walk_steps": wst["walk_steps"]},
             # tau <= 1 everywhere: only the closed-form l = 0, 1 terms, no traversal
             "closed_form_only": st["L_used"] <= 1,
         },
@@ -1021,10 +1040,15 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
             "kernel": "walk phase of the per-source waves (k_src_scan, k_src_walks, k_src_finish, "
                       "k_src_clear), timed by events per wave",
             "achieved": walk_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": walk_gbs / HBM_PEAK_GBS, "traffic": None,
+            "frac": walk_gbs / HBM_PEAK_GBS, "traffic": walk_traffic,
             "alg_bytes": st["prop_bytes"],
             "alg_bytes_note": "20 B per single-walk step (row bounds 8, neighbour id 4, column entry 8); "
                               "every access is random, so each moves at least a 64-byte line",
+            "traffic_note": ("FETCH_SIZE + WRITE_SIZE counters of k_src_walks, scaled by kernels of "
+                             f"known traffic: {per_step:.0f} B per single-walk step"
+                             if walk_traffic else None),
+            "traffic_TBps": (walk_traffic / (st["prop_ms"] * 1e-3) / 1e12
+                             if walk_traffic and st["prop_ms"] > 0 else None),
         },
         "cpu_baseline": None,
     }

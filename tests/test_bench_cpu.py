@@ -32,6 +32,18 @@ def test_measured_traffic_tracks_the_kernel_source():
     assert bench.PROP_TRAFFIC_BYTES > 0
 
 
+def test_walk_traffic_tracks_the_kernel_source():
+    h = hashlib.sha256()
+    for rel in bench.WALK_TRAFFIC_SOURCE[0]:
+        with open(os.path.join(bench.ROOT, rel), "rb") as f:
+            h.update(f.read())
+    digest = h.hexdigest()[:16]
+    want = bench.WALK_TRAFFIC_BYTES_PER_STEP if digest == bench.WALK_TRAFFIC_SOURCE[1] else None
+    assert bench.measured_walk_traffic_per_step() == want
+    assert digest == bench.WALK_TRAFFIC_SOURCE[1]
+    assert bench.WALK_TRAFFIC_BYTES_PER_STEP >= 20   # at least the algorithmic bytes
+
+
 def test_bench_refuses_more_than_one_gpu(capsys, monkeypatch):
     import json
     import sys
