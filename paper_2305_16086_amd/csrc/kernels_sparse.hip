@@ -214,10 +214,12 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
 
     // ---- (2)-(5) walk counts at this l (skipped where no half needs walks)
     // a forced switch step (tests, and a fixed tilde_tau option) skips Eq. 14 and
-    // evaluates the walk counts only where it stops
+    // evaluates the walk counts only where it stops.  Eq. 14 itself is not
+    // evaluated at l = 0: its left side is then d_i while each of the d_i halves
+    // needs at least one walk pair, so it cannot switch there.
     const bool forced = a.force_tilde >= 0;
     const int stop_forced = forced ? (a.force_tilde < taup ? a.force_tilde : taup) : -1;
-    const bool need = ell < taup && (!forced || ell == stop_forced);
+    const bool need = ell < taup && (forced ? ell == stop_forced : ell > 0);
     double rhs = 0.0;
     double rhoQ = 0.0;
     double maxNi = 0.0, minNi = 0.0;
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
     }
     // ---- (6) Eq. 14: switch when the next push costs more than the walks
     const bool done = forced ? ell >= stop_forced
-                             : (ell >= taup || static_cast<double>(vol) > rhs);
+                             : (ell >= taup || (need && static_cast<double>(vol) > rhs));
     if (done) {
       // clear the select keys, record the outcome
       for (int e = tid; e < cnt; e += kT) Qn[e] = 0;
