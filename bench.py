@@ -42,7 +42,7 @@ PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
 # factors (profiles/hbm_rmat22_k_src_walks.md); valid only for the sources they were taken on
 WALK_TRAFFIC_BYTES_PER_STEP = 252.0
 WALK_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_sparse.hip",
-                        "paper_2305_16086_amd/csrc/philox.hpp"), "c4dac1d474bcc7a2")
+                        "paper_2305_16086_amd/csrc/philox.hpp"), "212f265089e9f039")
 
 
 def traffic_source_digest(files=PROP_TRAFFIC_SOURCE[0]):

@@ -167,6 +167,19 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int w = blockIdx.x;
+  const int n = a.n;
+  {
+    // the final column of the slot's previous source, read by that wave's walks
+    // (earlier in stream order), is zeroed here instead of by a launch of its own
+    const int cnt_old = a.slot_ctl[2 * w];
+    if (cnt_old > 0) {
+      const size_t c = 2 * static_cast<size_t>(w) + static_cast<size_t>(a.slot_ctl[2 * w + 1]);
+      uint64_t* Qo = a.Q + c * static_cast<size_t>(n);
+      const int32_t* So = a.S + c * static_cast<size_t>(n);
+      for (int e = tid; e < cnt_old; e += kT) Qo[So[e]] = 0;
+    }
+    __syncthreads();
+  }
   const int64_t li = a.list_base + w;
   if (li >= a.nsrc) {
     if (tid == 0) {
@@ -175,7 +188,6 @@ __global__ __launch_bounds__(kT) void k_src_head(SrcArgs a) {
     }
     return;
   }
-  const int n = a.n;
   const int i = a.srcs ? a.srcs[li] : static_cast<int>(li);
   const int rb = a.rowptr[i], re = a.rowptr[i + 1];
   const int di = re - rb;
@@ -771,10 +783,9 @@ hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t* ds
   return hipGetLastError();
 }
 
-hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st) {
+hipError_t launch_src_walks(const SrcWalkArgs& a, hipStream_t st) {
   hipError_t e = launch_src_scan(a, st);
   if (e == hipSuccess) e = launch_src_walk_batch(a, st);
-  if (e == hipSuccess) e = launch_src_clear(a, nslots_used, st);
   return e;
 }
 

@@ -342,10 +342,11 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream
 hipError_t launch_nbr_volume(const DeviceGraph& g, int64_t* vol, hipStream_t st);
 // mm[0] = min(mm[0], min tau_row), mm[1] = max(mm[1], max tau_row)
 hipError_t launch_tau_range(int n, const int32_t* tau_row, unsigned long long* mm, hipStream_t st);
-// scan, walks, finish and the clearing of the wave's columns
-hipError_t launch_src_walks(const SrcWalkArgs& a, int nslots_used, hipStream_t st);
+// scan, walks and finish of a wave (its columns are cleared by the next head
+// that takes the slot, or by launch_src_clear after the last wave)
+hipError_t launch_src_walks(const SrcWalkArgs& a, hipStream_t st);
 // the same in parts: the chunk scan (ctl[0] = chunks), one batch of walks with
-// its finish pass, the clearing of the columns
+// its finish pass; and the clearing of every used slot's final column
 hipError_t launch_src_scan(const SrcWalkArgs& a, hipStream_t st);
 hipError_t launch_src_walk_batch(const SrcWalkArgs& a, hipStream_t st);
 hipError_t launch_src_clear(const SrcWalkArgs& a, int nslots_used, hipStream_t st);

@@ -127,6 +127,9 @@ int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   if (!B.Q_clean)
     HIP_TRY(sc::launch_fill_u64(B.Q, static_cast<int64_t>(2) * B.W * n, 0, st));
   HIP_TRY(sc::launch_fill_u64(reinterpret_cast<uint64_t*>(B.nr_slot), S2, 0, st));
+  // no slot holds a column to clear yet (the heads clear their slot's last one)
+  HIP_TRY(sc::launch_fill_u32(reinterpret_cast<uint32_t*>(B.slot_ctl), 2 * static_cast<int64_t>(B.W),
+                              0, st));
   HIP_TRY(sc::launch_fill_u32(reinterpret_cast<uint32_t*>(B.tilde_row), n, 0xFFFFFFFFu, st));
   HIP_TRY(sc::launch_gacc_init(g->d, B.tau_slot, 0, B.gacc, st));
 
@@ -201,12 +204,13 @@ int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
         wb.cend = std::min(total, c + wa.capacity);
         HIP_TRY(sc::launch_src_walk_batch(wb, st));
       }
-      HIP_TRY(sc::launch_src_clear(wa, cnt, st));
     } else {
-      HIP_TRY(sc::launch_src_walks(wa, cnt, st));
+      HIP_TRY(sc::launch_src_walks(wa, st));
     }
     if (walk_ev) HIP_TRY(hipEventRecord((*walk_ev)[2 * wave + 1], st));
   }
+  // the final columns of the slots' last sources (the first wave used the most slots)
+  HIP_TRY(sc::launch_src_clear(wa, static_cast<int>(std::min<int64_t>(B.W, nsrc)), st));
   HIP_TRY(sc::launch_combine(g->d, B.gacc, out_dev, st));
   HIP_TRY(sc::launch_trace(g->d, B.tau_slot, B.nr_slot, tau_o, nr_o, st));
   return SC_OK;
