@@ -29,8 +29,9 @@ SEED = 1
 BLOCK = 64
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "ba_100k_seed1_sampled_sc.npz")
-# HBM bytes per k_propagate launch on this workload from the FETCH_SIZE / WRITE_SIZE counters,
-# scaled by kernels of known traffic (profiles/hbm_ba100k_k_propagate.md); valid only for the
+# HBM bytes per k_propagate launch on this workload (the generator's node order) from the
+# FETCH_SIZE / WRITE_SIZE counters, scaled by kernels of known traffic
+# (profiles/hbm_ba100k_k_propagate.md); valid only for the
 # kernel sources they were taken on (first 16 hex digits of the SHA-256 of the files in order)
 PROP_TRAFFIC_BYTES = 419604636
 PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
@@ -43,6 +44,15 @@ PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
 WALK_TRAFFIC_BYTES_PER_STEP = 252.0
 WALK_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_sparse.hip",
                         "paper_2305_16086_amd/csrc/philox.hpp"), "212f265089e9f039")
+
+
+def node_order_flag(sc, order):
+    """Build flag and JSON description of a --node-order value."""
+    if order == "degree":
+        return sc.SC_DEGREE_ORDER, "degree (SC_DEGREE_ORDER: stored by descending degree)"
+    if order == "bfs":
+        return sc.SC_BFS_ORDER, "bfs (SC_BFS_ORDER: stored in breadth-first order from the top hub)"
+    return 0, "the generator's"
 
 
 def traffic_source_digest(files=PROP_TRAFFIC_SOURCE[0]):
@@ -92,9 +102,10 @@ def parse():
                    help="rmat, orkut: Eq. 14 as printed (0) or weighing walks by their steps (1)")
     p.add_argument("--full-call-limit", type=float, default=150.0,
                    help="rmat, orkut: time the whole call when the sample extrapolates below this (s)")
-    p.add_argument("--degree-order", type=int, default=None, choices=[0, 1],
-                   help="build the graph with SC_DEGREE_ORDER (nodes stored by descending "
-                        "degree); default: on for rmat and orkut, off for plain")
+    p.add_argument("--node-order", default=None, choices=["generator", "degree", "bfs"],
+                   help="how the library stores the nodes (build flags SC_DEGREE_ORDER, "
+                        "SC_BFS_ORDER; the input and the ids at the interface are unchanged); "
+                        "default: the generator's for plain, degree for rmat and orkut")
     p.add_argument("--rmat-sources", type=int, default=4096,
                    help="rmat: uniform random sources timed (the full call is extrapolated)")
     p.add_argument("--no-extras", action="store_true",
@@ -929,9 +940,10 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
     n, u, v = graph
     m = len(u)
     print(f"[{name}] n={n} m={m} ({gen_s:.0f} s)", file=sys.stderr, flush=True)
-    degree_order = a.degree_order is None or a.degree_order == 1
+    order = a.node_order or "degree"
+    order_flag, order_desc = node_order_flag(sc, order)
     t0 = time.perf_counter()
-    g = sc.sc_build_graph(n, u, v, sc.SC_DEGREE_ORDER if degree_order else 0)
+    g = sc.sc_build_graph(n, u, v, order_flag)
     build_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     lam = sc.sc_lambda_star(g)
@@ -1003,7 +1015,7 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
     call_s = full["s"] if full else full_s
     # counters were taken for the R-MAT sample in degree order only
     per_step = (measured_walk_traffic_per_step()
-                if name == "rmat_s22" and degree_order and full is None else None)
+                if name == "rmat_s22" and order == "degree" and full is None else None)
     walk_traffic = per_step * st["walk_steps"] if per_step else None
     line = {
         "metric": ("all-edge SC edges/sec (per-source TGT+, whole call)" if full else
@@ -1021,8 +1033,7 @@ def sampled_source_form(a, name, workload, graph, gen_s, eps, golden):
                        ("; the whole call then timed (value)" if full else
                         "; the value is the extrapolation")),
             "full_call": full,
-            "node_order": ("degree (SC_DEGREE_ORDER: stored by descending degree, the "
-                           "caller's ids at the interface)" if degree_order else "the generator's"),
+            "node_order": order_desc,
             "sample_sources_per_s": len(src) / dt, "lambda_star": lam,
             "lambda_converged": st["lambda_converged"], "L_used": st["L_used"],
             "L_min": st["L_min"], "L_capped": st["L_capped"], "tilde_min": st["tilde_min"],
@@ -1093,7 +1104,8 @@ def main():
     m = len(u)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    g = sc.sc_build_graph(n, u, v, sc.SC_DEGREE_ORDER if a.degree_order == 1 else 0)
+    order_flag, order_desc = node_order_flag(sc, a.node_order or "generator")
+    g = sc.sc_build_graph(n, u, v, order_flag)
     out = torch.empty(m, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
@@ -1180,7 +1192,7 @@ def main():
                         "FP64 per-edge sums, block 64",
             "max_abs_err_sampled": err,
             "err_sample": "2048 edges, exact SC by float64 block-PCG" if err is not None else None,
-            "node_order": "degree (SC_DEGREE_ORDER)" if a.degree_order == 1 else "the generator's",
+            "node_order": order_desc,
             "L_used": last["L_used"], "L_min": last["L_min"],
             "tilde_tau": last["tilde_tau"], "lambda_star": last["lambda_star"],
             "lambda_converged": last["lambda_converged"], "L_capped": last["L_capped"],
@@ -1197,7 +1209,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            # the counters were taken with the nodes in the generator's order
+            "traffic": measured_traffic() if (a.node_order or "generator") == "generator" else None,
             "avg_launch_us": avg_launch_us,
             "launches": launches,
             "timed_launches": timed,

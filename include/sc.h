@@ -58,6 +58,9 @@ enum {
 #define SC_DEGREE_ORDER 0x4u /* store the nodes renumbered by descending degree (ties by id)
                                 for the locality of the walks and traversals; see
                                 sc_build_graph (sc_build_graph only) */
+#define SC_BFS_ORDER 0x8u    /* store the nodes renumbered in breadth-first order from the
+                                highest-degree node, for the locality of the source blocks;
+                                see sc_build_graph (sc_build_graph only) */
 
 /* run flags (sc_options.flags) */
 #define SC_DEVICE_PTRS 0x1u  /* out / trace arrays are device pointers */
@@ -158,17 +161,23 @@ void sc_default_options(sc_options* o);
  * bipartite (SC_EBIPARTITE).  With SC_MERGE_DUPS repeated edges report the
  * same value.  The CSR, degree and half-edge maps are uploaded to the
  * current HIP device.  n >= 2, 1 <= m, 2m < 2^31.
- * SC_DEGREE_ORDER: the handle stores the graph with node x renumbered to its
- * rank by descending degree (ties by ascending x), so the rows that walks and
- * gathers visit most share cache lines.  The graph is the same; every node
- * id the API takes or returns stays the caller's (source lists,
- * tilde_tau_out, spectra, walk traces) and per-edge results keep the input
- * order.  A flagged handle computes exactly what an unflagged handle built
- * on the renumbered edge list computes (same sums, same walks: the Philox
- * counters and the neighbour order are those of the renumbered graph), so
- * its results differ from an unflagged handle's on the caller's labels by
- * rounding order and the walks' randomness only.  Costs 16 bytes per edge of
- * host memory during the build and 4 bytes per node of device memory.
+ * Node orders (at most one of the two flags; SC_EINVAL for both):
+ * SC_DEGREE_ORDER stores node x as its rank by descending degree (ties by
+ * ascending x), so the rows that walks and pushes visit most share cache
+ * lines; SC_BFS_ORDER stores the nodes in the order a breadth-first search
+ * visits them, started at the highest-degree node (the lowest id among
+ * equals) and taking each node's neighbours in ascending id, so a block of
+ * consecutive sources lies close together in the graph (nodes it cannot
+ * reach keep ascending id after the others; such a graph is rejected as
+ * disconnected anyway).  The graph is the same; every node id the API takes
+ * or returns stays the caller's (source lists, tilde_tau_out, spectra, walk
+ * traces) and per-edge results keep the input order.  A flagged handle
+ * computes exactly what an unflagged handle built on the renumbered edge
+ * list computes (same sums, same walks: the Philox counters and the
+ * neighbour order are those of the renumbered graph), so its results differ
+ * from an unflagged handle's on the caller's labels by rounding order and
+ * the walks' randomness only.  Costs up to 24 bytes per edge of host memory
+ * during the build and 4 bytes per node of device memory.
  */
 int sc_build_graph(int64_t n, int64_t m, const int64_t* u_host, const int64_t* v_host,
                    unsigned flags, sc_graph** out);
@@ -198,9 +207,9 @@ int sc_lambda_star(sc_graph* g, double* lam);
  * of the current node's row (neighbours in ascending id order).
  * nodes_host (host, 2 * length int32, caller-owned): nodes_host[t-1] is the
  * node after step t from i, nodes_host[length + t-1] the same from j.
- * i and j need not be adjacent.  On a handle built with SC_DEGREE_ORDER the
- * walk is the renumbered graph's (counters and rows in its ids), and i, j and
- * the nodes returned are the caller's ids.  Errors: SC_EINVAL for ids out of range,
+ * i and j need not be adjacent.  On a handle built with SC_DEGREE_ORDER or
+ * SC_BFS_ORDER the walk is the renumbered graph's (counters and rows in its
+ * ids), and i, j and the nodes returned are the caller's ids.  Errors: SC_EINVAL for ids out of range,
  * r outside [0, 2^32), length outside [0, 2^20]; SC_ENOMEM / SC_EHIP from the
  * device (nodes_host is then not written).
  */
@@ -404,7 +413,7 @@ typedef struct sc_batch sc_batch;
  * error text names the failing graph) plus the sliced neighbour lists the
  * batch kernel reads.  n[g], m[g]: sizes; u_host[g], v_host[g]: the m[g]
  * edge endpoints of graph g (int64, host, copied).  flags as sc_build_graph,
- * except SC_DEGREE_ORDER (SC_EINVAL). */
+ * except SC_DEGREE_ORDER and SC_BFS_ORDER (SC_EINVAL). */
 int sc_build_batch(int G, const int64_t* n, const int64_t* m, const int64_t* const* u_host,
                    const int64_t* const* v_host, unsigned flags, sc_batch** out);
 

@@ -363,34 +363,92 @@ int sc::graph_from_csr(HostCSR& h, sc_graph** out) {
   return SC_OK;
 }
 
+namespace {
+
+// Breadth-first visiting order of the nodes (ids valid, n >= 1): started at
+// the highest-degree node (lowest id among equals), each node's neighbours
+// taken in ascending id; unreached nodes follow in ascending id.
+void bfs_order(int64_t n, int64_t m, const int64_t* u, const int64_t* v, std::vector<int32_t>& label) {
+  std::vector<int64_t> off(n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    ++off[u[e] + 1];
+    ++off[v[e] + 1];
+  }
+  for (int64_t x = 0; x < n; ++x) off[x + 1] += off[x];
+  std::vector<int32_t> adj(static_cast<size_t>(2 * m));
+  {
+    // rows in edge order, then transposed: walking the rows in ascending x and
+    // appending x to each neighbour's row leaves every row in ascending id
+    std::vector<int32_t> first(static_cast<size_t>(2 * m));
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < m; ++e) {
+      first[pos[u[e]]++] = static_cast<int32_t>(v[e]);
+      first[pos[v[e]]++] = static_cast<int32_t>(u[e]);
+    }
+    pos.assign(off.begin(), off.end() - 1);
+    for (int64_t x = 0; x < n; ++x)
+      for (int64_t k = off[x]; k < off[x + 1]; ++k) adj[pos[first[k]]++] = static_cast<int32_t>(x);
+  }
+  int64_t s = 0;
+  for (int64_t x = 1; x < n; ++x)
+    if (off[x + 1] - off[x] > off[s + 1] - off[s]) s = x;
+  std::vector<unsigned char> seen(n, 0);
+  label.clear();
+  label.reserve(n);
+  seen[s] = 1;
+  label.push_back(static_cast<int32_t>(s));
+  for (size_t q = 0; q < label.size(); ++q) {
+    const int32_t x = label[q];
+    for (int64_t k = off[x]; k < off[x + 1]; ++k) {
+      const int32_t y = adj[k];
+      if (!seen[y]) {
+        seen[y] = 1;
+        label.push_back(y);
+      }
+    }
+  }
+  for (int64_t x = 0; x < n; ++x)
+    if (!seen[x]) label.push_back(static_cast<int32_t>(x));
+}
+
+}  // namespace
+
 extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                               unsigned flags, sc_graph** out) {
   if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
   *out = nullptr;
+  const unsigned order_flags = flags & (SC_DEGREE_ORDER | SC_BFS_ORDER);
+  if (order_flags == (SC_DEGREE_ORDER | SC_BFS_ORDER))
+    return fail(SC_EINVAL, "SC_DEGREE_ORDER and SC_BFS_ORDER exclude each other");
+  const unsigned build_flags = flags & ~(SC_DEGREE_ORDER | SC_BFS_ORDER);
   sc::HostCSR h;
-  bool ranges_ok = (flags & SC_DEGREE_ORDER) && u && v && n >= 2 && n < (1ll << 31) && m >= 1 &&
+  bool ranges_ok = order_flags && u && v && n >= 2 && n < (1ll << 31) && m >= 1 &&
                    2 * m < (1ll << 31);
   for (int64_t e = 0; ranges_ok && e < m; ++e)
     ranges_ok = u[e] >= 0 && u[e] < n && v[e] >= 0 && v[e] < n;
   if (!ranges_ok) {
     // the caller's ids (or input errors, reported by the build)
-    const int rc = sc::build_host_csr(n, m, u, v, flags & ~SC_DEGREE_ORDER, h);
+    const int rc = sc::build_host_csr(n, m, u, v, build_flags, h);
     if (rc) return rc;
     return sc::graph_from_csr(h, out);
   }
-  // renumber by descending degree, ties by ascending id; the edge order is kept
+  // renumber (stored node y is the caller's label[y]); the edge order is kept
   std::vector<int32_t> rank, label;
   std::vector<int64_t> u2, v2;
   try {
-    std::vector<int64_t> deg(n, 0);
-    for (int64_t e = 0; e < m; ++e) {
-      ++deg[u[e]];
-      ++deg[v[e]];
+    if (order_flags == SC_BFS_ORDER) {
+      bfs_order(n, m, u, v, label);
+    } else {   // descending degree, ties by ascending id
+      std::vector<int64_t> deg(n, 0);
+      for (int64_t e = 0; e < m; ++e) {
+        ++deg[u[e]];
+        ++deg[v[e]];
+      }
+      label.resize(n);
+      std::iota(label.begin(), label.end(), 0);
+      std::stable_sort(label.begin(), label.end(),
+                       [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
     }
-    label.resize(n);
-    std::iota(label.begin(), label.end(), 0);
-    std::stable_sort(label.begin(), label.end(),
-                     [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
     rank.resize(n);
     for (int64_t y = 0; y < n; ++y) rank[label[y]] = static_cast<int32_t>(y);
     u2.resize(m);
@@ -402,7 +460,7 @@ extern "C" int sc_build_graph(int64_t n, int64_t m, const int64_t* u, const int6
   } catch (const std::bad_alloc&) {
     return fail(SC_ENOMEM, "host allocation failed");
   }
-  int rc = sc::build_host_csr(n, m, u2.data(), v2.data(), flags & ~SC_DEGREE_ORDER, h);
+  int rc = sc::build_host_csr(n, m, u2.data(), v2.data(), build_flags, h);
   if (rc) return rc;
   u2 = std::vector<int64_t>();
   v2 = std::vector<int64_t>();

@@ -644,7 +644,8 @@ extern "C" int sc_build_batch(int G, const int64_t* n, const int64_t* m,
   if (!out) return fail(SC_EINVAL, "out handle pointer is NULL");
   *out = nullptr;
   if (G < 1 || !n || !m || !u_host || !v_host) return fail(SC_EINVAL, "bad batch arguments");
-  if (flags & SC_DEGREE_ORDER) return fail(SC_EINVAL, "SC_DEGREE_ORDER applies to sc_build_graph only");
+  if (flags & (SC_DEGREE_ORDER | SC_BFS_ORDER))
+    return fail(SC_EINVAL, "SC_DEGREE_ORDER and SC_BFS_ORDER apply to sc_build_graph only");
   sc_batch* b = new (std::nothrow) sc_batch();
   if (!b) return fail(SC_ENOMEM, "host allocation failed");
   auto bail = [&](int rc) {

@@ -26,7 +26,8 @@ SC_EHIP = -7
 SC_ENOTIMPL = -8
 
 SC_MERGE_DUPS = 0x2
-SC_DEGREE_ORDER = 0x4   # build flag (same bit as the run flag SC_TIME_KERNELS)
+SC_DEGREE_ORDER = 0x4   # build flags (same bits as the run flags SC_TIME_KERNELS and
+SC_BFS_ORDER = 0x8      # SC_GRAPH_REPLAY)
 SC_DEVICE_PTRS = 0x1
 SC_TIME_KERNELS = 0x4
 SC_GRAPH_REPLAY = 0x8

@@ -1,5 +1,6 @@
-"""GPU checks of SC_DEGREE_ORDER: a handle that stores the graph with its nodes
-renumbered by descending degree (ties by id).
+"""GPU checks of the node orders SC_DEGREE_ORDER and SC_BFS_ORDER: a handle that
+stores the graph with its nodes renumbered by descending degree (ties by id),
+or in breadth-first order from the highest-degree node.
 
 The flagged handle must compute exactly what an unflagged handle computes on
 the renumbered edge list (same CSR, same sums, same walks), while every node
@@ -16,7 +17,8 @@ id at the interface stays the caller's:
 * the estimate within eps of the exact SC (labelling does not change SC).
 
 The renumbering itself is recomputed here from its definition (numpy stable
-argsort of the negated degrees).
+argsort of the negated degrees; a plain breadth-first search over sorted
+neighbour lists).
 """
 import numpy as np
 import pytest
@@ -41,20 +43,40 @@ def graph():
     return gg.rmat_lcc(10, 8, seed=3)
 
 
-def renumbering(n, u, v):
+def renumbering(n, u, v, kind):
     deg = np.bincount(np.concatenate([u, v]), minlength=n)
-    label = np.argsort(-deg, kind="stable")   # stored node y is the caller's label[y]
+    if kind == "degree":
+        label = np.argsort(-deg, kind="stable")   # stored node y is the caller's label[y]
+    else:
+        adj = [[] for _ in range(n)]
+        for a, b in zip(u.tolist(), v.tolist()):
+            adj[a].append(b)
+            adj[b].append(a)
+        start = int(np.argmax(deg))   # the first of the highest degree
+        seen = np.zeros(n, bool)
+        seen[start] = True
+        order = [start]
+        for x in order:               # grows while it is walked
+            for y in sorted(adj[x]):
+                if not seen[y]:
+                    seen[y] = True
+                    order.append(y)
+        order += [x for x in range(n) if not seen[x]]
+        label = np.array(order)
     rank = np.empty(n, np.int64)
     rank[label] = np.arange(n)
     return rank, label
 
 
-@pytest.fixture(scope="module")
-def pair(sc, graph):
+@pytest.fixture(scope="module", params=["degree", "bfs"])
+def pair(sc, graph, request):
     n, u, v = graph
-    rank, label = renumbering(n, u, v)
-    print(f"[gpu] degree order: n={n} m={len(u)}", flush=True)
-    gf = sc.sc_build_graph(n, u, v, sc.SC_DEGREE_ORDER)
+    kind = request.param
+    rank, label = renumbering(n, u, v, kind)
+    assert not np.array_equal(label, np.arange(n))   # the order does change the ids
+    print(f"[gpu] node order {kind}: n={n} m={len(u)}", flush=True)
+    flag = sc.SC_DEGREE_ORDER if kind == "degree" else sc.SC_BFS_ORDER
+    gf = sc.sc_build_graph(n, u, v, flag)
     gr = sc.sc_build_graph(n, rank[u], rank[v])
     yield gf, gr, rank, label
     gf.free()

@@ -60,11 +60,13 @@ def test_validation_rejects_invalid_graphs():
     assert "bipartite" in sc.sc_last_error()
 
 
-def test_validation_with_degree_order_reports_the_same_errors():
-    """SC_DEGREE_ORDER renumbers after the id checks: every invalid graph gets the
-    code it gets without the flag (edge indices in the caller's order)."""
+@pytest.mark.parametrize("order", ["degree", "bfs"])
+def test_validation_with_node_order_reports_the_same_errors(order):
+    """SC_DEGREE_ORDER and SC_BFS_ORDER renumber after the id checks: every invalid
+    graph gets the code it gets without the flag (edge indices in the caller's
+    order)."""
     from paper_2305_16086_amd import sc
-    f = sc.SC_DEGREE_ORDER
+    f = sc.SC_DEGREE_ORDER if order == "degree" else sc.SC_BFS_ORDER
     assert _code(3, [0, 1, 2], [1, 2, 2], f) == sc.SC_ESELFLOOP
     assert "edge 2" in sc.sc_last_error()
     assert _code(3, [0, 1, 0, 1], [1, 2, 2, 0], f) == sc.SC_EDUP
@@ -77,12 +79,21 @@ def test_validation_with_degree_order_reports_the_same_errors():
     assert _code(n, u, v, f) == sc.SC_EBIPARTITE
 
 
-def test_batch_rejects_degree_order():
+def test_node_orders_exclude_each_other():
     from paper_2305_16086_amd import sc
+    n, u, v = gg.complete_graph(4)
+    assert _code(n, u, v, sc.SC_DEGREE_ORDER | sc.SC_BFS_ORDER) == sc.SC_EINVAL
+    assert "exclude" in sc.sc_last_error()
+
+
+@pytest.mark.parametrize("order", ["degree", "bfs"])
+def test_batch_rejects_node_order(order):
+    from paper_2305_16086_amd import sc
+    f = sc.SC_DEGREE_ORDER if order == "degree" else sc.SC_BFS_ORDER
     with pytest.raises(sc.ScError) as ei:
-        sc.sc_build_batch([gg.complete_graph(4)], sc.SC_DEGREE_ORDER)
+        sc.sc_build_batch([gg.complete_graph(4)], f)
     assert ei.value.code == sc.SC_EINVAL
-    assert "SC_DEGREE_ORDER" in sc.sc_last_error()
+    assert "sc_build_graph only" in sc.sc_last_error()
 
 
 def test_validation_of_even_cycle_plus_chord_is_not_bipartite_error():
