@@ -578,7 +578,7 @@ extern "C" int sc_all_edges_static(sc_graph* g, double eps, int L, const sc_opti
       HIP_TRY(hipMemcpyAsync(o->tilde_tau_out, B.tilde_row, n * sizeof(int32_t),
                              hipMemcpyDeviceToDevice, stream));
   }
-  last.clean = true;   // in stream order, the walks' last pass clears every column it used
+  last.clean = true;   // in stream order, the call's last clear zeroes every column it used
   if (st) {
     unsigned long long tot[kTotals] = {};
     HIP_TRY(hipMemcpyAsync(tot, B.totals, sizeof(tot), hipMemcpyDeviceToHost, stream));
