@@ -43,7 +43,7 @@ PROP_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_tgt.hip",
 # factors (profiles/hbm_rmat22_k_src_walks.md); valid only for the sources they were taken on
 WALK_TRAFFIC_BYTES_PER_STEP = 252.0
 WALK_TRAFFIC_SOURCE = (("paper_2305_16086_amd/csrc/kernels_sparse.hip",
-                        "paper_2305_16086_amd/csrc/philox.hpp"), "212f265089e9f039")
+                        "paper_2305_16086_amd/csrc/philox.hpp"), "250d6397ae5e35f7")
 
 
 def node_order_flag(sc, order):

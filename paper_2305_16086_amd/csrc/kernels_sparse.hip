@@ -633,20 +633,52 @@ __global__ __launch_bounds__(256) void k_src_walks(SrcWalkArgs a) {
   }
 }
 
-// gacc[k] += (chunk sums of half p in chunk order) / n_r
+// The half's chunks inside this batch: [lo, hi), stored from part[lo - cb].
+__device__ inline bool finish_range(const SrcWalkArgs& a, long long p, long long* cb,
+                                    long long* lo, long long* hi) {
+  if (a.nr_pos[p] <= 0) return false;
+  *cb = a.cend < 0 ? 0 : a.cbeg;
+  *lo = max(a.chunk_off[p], *cb);
+  *hi = a.cend < 0 ? a.chunk_off[p + 1] : min(a.chunk_off[p + 1], a.cend);
+  return *lo < *hi;
+}
+
+// gacc[k] += (chunk sums of half p in chunk order) / n_r, one thread per half
+// with at most finish_seg chunks in the batch
 __global__ __launch_bounds__(256) void k_src_finish(SrcWalkArgs a) {
   const long long p = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (p >= a.P || (a.cend < 0 && a.ctl[1] == 0)) return;
-  const long long nr = a.nr_pos[p];
-  if (nr <= 0) return;
-  // the half's chunks inside this batch, in chunk order
-  const long long cb = a.cend < 0 ? 0 : a.cbeg;
-  const long long lo = max(a.chunk_off[p], cb);
-  const long long hi = a.cend < 0 ? a.chunk_off[p + 1] : min(a.chunk_off[p + 1], a.cend);
-  if (lo >= hi) return;
+  long long cb, lo, hi;
+  if (!finish_range(a, p, &cb, &lo, &hi) || hi - lo > a.finish_seg) return;
   double s = 0.0;
   for (long long c = lo; c < hi; ++c) s += a.part[c - cb];
-  a.gacc[a.pos_slot[p]] += s / static_cast<double>(nr);
+  a.gacc[a.pos_slot[p]] += s / static_cast<double>(a.nr_pos[p]);
+}
+
+// The same for the halves with more chunks: a workgroup per half, each thread
+// summing one fixed segment of ceil(chunks / 256) in order, then the 256
+// segment sums in order (the order depends only on the chunk count)
+__global__ __launch_bounds__(256) void k_src_finish_long(SrcWalkArgs a) {
+  __shared__ double s_seg[256];
+  if (a.cend < 0 && a.ctl[1] == 0) return;
+  const int tid = threadIdx.x;
+  for (long long p = blockIdx.x; p < a.P; p += gridDim.x) {
+    long long cb, lo, hi;
+    if (!finish_range(a, p, &cb, &lo, &hi) || hi - lo <= a.finish_seg) continue;
+    const long long seg = (hi - lo + 255) / 256;
+    const long long c0 = lo + tid * seg;
+    const long long c1 = min(hi, c0 + seg);
+    double s = 0.0;
+    for (long long c = c0; c < c1; ++c) s += a.part[c - cb];
+    s_seg[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int q = 0; q < 256; ++q) t += s_seg[q];
+      a.gacc[a.pos_slot[p]] += t / static_cast<double>(a.nr_pos[p]);
+    }
+    __syncthreads();
+  }
 }
 
 // zero the slot's final column over its support list
@@ -762,6 +794,9 @@ hipError_t launch_src_walk_batch(const SrcWalkArgs& a, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_src_finish<<<static_cast<unsigned>((a.P + 255) / 256), 256, 0, st>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_src_finish_long<<<static_cast<unsigned>(std::min<int64_t>(a.P, 1024)), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -332,6 +332,9 @@ struct SrcWalkArgs {
   // index 0); cend < 0: all chunks at once, or one wave per half when they do
   // not fit the buffer (ctl[1] == 0)
   int64_t cbeg = 0, cend = -1;
+  // a half with more chunks than this in the batch is summed by a whole
+  // workgroup (fixed segments, then the segment sums in order)
+  int64_t finish_seg = 4096;
 };
 
 hipError_t launch_src_head(const SrcArgs& a, int grid, hipStream_t st);

@@ -180,6 +180,8 @@ int enqueue_per_source(sc_graph* g, double eps, int L, const sc_options& o, doub
   wa.gacc = B.gacc;
   wa.k0 = static_cast<unsigned>(o.seed & 0xFFFFFFFFull);
   wa.k1 = static_cast<unsigned>(o.seed >> 32);
+  if (const char* f = std::getenv("SC_SOURCE_FINISH_SEG"))   // smaller segments (tests)
+    wa.finish_seg = std::max<int64_t>(1, std::atoll(f));
 
   auto at = [&](int64_t k) -> int64_t { return hoff ? (*hoff)[k] : int64_t(g->rowptr_h[k]); };
   int64_t wave = 0;

@@ -242,6 +242,25 @@ def test_many_waves_and_walk_fallback_agree(sc, monkeypatch):
     np.testing.assert_allclose(out3, ref, atol=TOL, rtol=0)
 
 
+def test_long_finish_path_agrees(sc, monkeypatch):
+    # halves with more chunks than SC_SOURCE_FINISH_SEG are summed by a whole
+    # workgroup in fixed segments; with a segment of one chunk every half with
+    # two or more chunks takes that path, also across walk batches
+    graph = gg.tree_plus_gnp(500, 8.0, 8)
+    ref, _, _, tt, nr = run_ps(sc, graph, 0.03)
+    assert nr.max() > 64 * 3                                      # halves of several chunks
+    monkeypatch.setenv("SC_SOURCE_FINISH_SEG", "1")
+    out, _, _, tt2, nr2 = run_ps(sc, graph, 0.03)
+    np.testing.assert_array_equal(nr2, nr)
+    np.testing.assert_array_equal(tt2, tt)
+    np.testing.assert_allclose(out, ref, atol=TOL, rtol=0)
+    monkeypatch.setenv("SC_SOURCE_PART_CAPACITY", "5")            # batches of five chunks
+    out3, _, _, _, _ = run_ps(sc, graph, 0.03)
+    np.testing.assert_allclose(out3, ref, atol=TOL, rtol=0)
+    out4, _, _, _, _ = run_ps(sc, graph, 0.03)
+    np.testing.assert_array_equal(out4, out3)                     # fixed order
+
+
 def test_options_keep_no_source_list(sc):
     # a call with sources= leaves the caller's options as they were: reusing them
     # without sources= runs every source
