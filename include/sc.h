@@ -280,7 +280,8 @@ int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double*
                     sc_stats* st);
 /*
  * With SC_PER_SOURCE (TGT+): every source i starts at p_0(., i) = e_i and,
- * at l = 0, 1, ..., tests Eq. 14: the volume of the nodes with p_l(v, i) != 0
+ * at l = 1, 2, ... (at l = 0 the volume d_i cannot exceed the d_i halves' walk
+ * pairs), tests Eq. 14: the volume of the nodes with p_l(v, i) != 0
  * against the walk pairs (switch_rule 0) or walk steps (1) that stopping at l
  * would need (Eq. 13 with chi of Algorithm 3 at q = p_l(., i)); the first l
  * where the volume is larger, or l = max_j tau_ij, is tilde_tau_i (recorded in
@@ -296,7 +297,9 @@ int sc_all_edges_ex(sc_graph* g, double eps, int L, const sc_options* o, double*
  * push_edges, walks, walk_steps; with SC_TIME_KERNELS, prop_ms is the time of
  * the waves' walk phases (events on the stream), prop_launches = prop_timed =
  * waves and prop_bytes = 20 bytes per single-walk step (row bounds, neighbour
- * id, column entry).
+ * id, column entry).  Environment (tests): SC_SOURCE_PART_CAPACITY caps the
+ * walk chunk-sum buffer (smaller walk batches), SC_SOURCE_FINISH_SEG the chunk
+ * count of a half above which a workgroup sums its chunk sums (default 4096).
  */
 
 /*
